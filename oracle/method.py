@@ -1,0 +1,209 @@
+"""The hierarchical master/slave iteration, step by step (oracle).
+
+Test infrastructure only (see the package docstring).
+
+One outer iteration, in the paper's order (section 2, section 3 flowchart
+description):
+
+  1. residual of the current displacement and the stop test of Eq. 19;
+  2. per set I, local relaxation with the displacements outside the set held
+     at their last values (Eq. 11-12), giving the relaxation increment
+     u^RD - u^old (Eq. 13);
+  3. the q = 9 incremental modes of every set: translations (Eq. 9),
+     constant-gradient modes about the set's representative node (Eq. 10),
+     the relaxation increment and its two gradient-weighted copies (Eq. 13-14);
+  4. upper-level stiffness K_a = U^T K U (Eq. 6) and force
+     P_a = U^T (p - K u^old) (Eq. 7);
+  5. solve the upper-level system (Eq. 8);
+  6. update u = u^old + U a (Eq. 3).
+
+Both inner solves are exact here, as in the paper (a direct sparse solver
+for the local relaxation, section 2.2 end; a single-processor solver for the
+upper level, section 2.1).  Sets are E x E node tiles of the (i, j) index
+grid; the last row/column of tiles is narrower when E does not divide the
+lattice side.  Every mode is zero on clamped DOFs, so supports never move.
+
+Readings where the paper is silent (stated, not derived):
+  * representative node of a set = centroid of the tile's nodes in physical
+    coordinates, and the gradient modes are scaled by 1/(E/2); in exact
+    arithmetic neither choice changes the iterates (span{1, x - c} =
+    span{1, x}, span{d, (x - c) d} = span{d, x d});
+  * the upper-level matrix can be singular (dependent modes, e.g. a set
+    whose relaxation increment is zero); it is consistent, so its
+    minimum-norm solution is taken after a symmetric Jacobi scaling, and
+    U a is then the same for every minimiser.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .lattice import node_xy
+from .solve import System, energy, rel_residuals, residual
+
+Q = 9   # modes per set on the hot path: Eq. 9 (2), Eq. 10 (4), Eq. 13-14 (3)
+
+
+@dataclasses.dataclass
+class Sets:
+    nx: int
+    ny: int
+    E: int
+    mx: int                  # tiles along i
+    my: int                  # tiles along j
+    of_node: np.ndarray      # int [ny*nx] set id of every node, id = J*mx + I
+    xc: np.ndarray           # float [M] representative node x
+    yc: np.ndarray           # float [M] representative node y
+    scale: float             # gradient-mode length scale
+
+    @property
+    def M(self) -> int:
+        return self.mx * self.my
+
+
+def make_sets(nx: int, ny: int, E: int, rep_shift=(0.0, 0.0)) -> Sets:
+    """E x E tiles of the node index grid; the representative node is the
+    tile's centroid, optionally shifted by rep_shift (for invariance checks)."""
+    mx, my = -(-nx // E), -(-ny // E)
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    of_node = ((j // E) * mx + (i // E)).reshape(-1)
+    x, y = node_xy(nx, ny)
+    M = mx * my
+    cnt = np.bincount(of_node, minlength=M).astype(np.float64)
+    xc = np.bincount(of_node, weights=x.reshape(-1), minlength=M) / cnt + rep_shift[0]
+    yc = np.bincount(of_node, weights=y.reshape(-1), minlength=M) / cnt + rep_shift[1]
+    return Sets(nx, ny, E, mx, my, of_node, xc, yc, E / 2.0)
+
+
+class LocalSolver:
+    """Exact local relaxation of Eq. 12 for every set.
+
+    For set I, k^Inner is the block of K on the set's free DOFs (its entries
+    are those of the global matrix, section 2.2), so
+        k^Inner u^RD = p^Inner - k^Outer u^Outer,old
+    gives u^RD - u^old = (k^Inner)^-1 (p - K u^old)|_I.  The factors are
+    computed once and reused, as section 2.2 describes."""
+
+    def __init__(self, sys_: System, sets: Sets):
+        self.idx = []
+        self.lu = []
+        dof_set = np.repeat(sets.of_node, 2)
+        for I in range(sets.M):
+            idx = np.flatnonzero((dof_set == I) & sys_.free)
+            self.idx.append(idx)
+            if idx.size:
+                kin = sys_.K[idx][:, idx].tocsc()
+                self.lu.append(spla.splu(kin))
+            else:
+                self.lu.append(None)
+
+    def relax(self, r: np.ndarray) -> np.ndarray:
+        """Relaxation increment (Eq. 13) of every set, stacked into one vector."""
+        d = np.zeros_like(r)
+        for idx, lu in zip(self.idx, self.lu):
+            if lu is not None:
+                d[idx] = lu.solve(r[idx])
+        return d
+
+
+def mode_matrix(sys_: System, sets: Sets, delta: np.ndarray) -> sp.csr_matrix:
+    """U = [u_hat_k^(I)] as a sparse 2N x (Q*M) matrix, column Q*I + (k-1).
+
+    Modes 1-2 translations (Eq. 9); 3-6 (x - x_I, 0), (y - y_I, 0),
+    (0, x - x_I), (0, y - y_I) (Eq. 10), scaled; 7 the relaxation increment
+    (Eq. 13); 8-9 its copies weighted by (x - x_I) and (y - y_I) (Eq. 14)."""
+    nn = sets.nx * sets.ny
+    x, y = node_xy(sets.nx, sets.ny)
+    I = sets.of_node
+    xi = (x.reshape(-1) - sets.xc[I]) / sets.scale
+    eta = (y.reshape(-1) - sets.yc[I]) / sets.scale
+    free_node = sys_.free[0::2]
+    dx, dy = delta[0::2], delta[1::2]
+    one, zero = np.ones(nn), np.zeros(nn)
+    comps = [  # (x-component, y-component) of modes 1..9 at every node
+        (one, zero), (zero, one),
+        (xi, zero), (eta, zero), (zero, xi), (zero, eta),
+        (dx, dy), (xi * dx, xi * dy), (eta * dx, eta * dy),
+    ]
+    rows, cols, vals = [], [], []
+    node = np.arange(nn)
+    for k, (cx, cy) in enumerate(comps):
+        for c, comp in ((0, cx), (1, cy)):
+            v = np.where(free_node, comp, 0.0)
+            nz = v != 0.0
+            rows.append(2 * node[nz] + c)
+            cols.append(Q * I[nz] + k)
+            vals.append(v[nz])
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(2 * nn, Q * sets.M)).tocsr()
+
+
+def upper_level(sys_: System, U: sp.csr_matrix, u_old: np.ndarray):
+    """K_a = U^T K U (Eq. 6) and P_a = U^T (p - K u^old) (Eq. 7)."""
+    Kc = (U.T @ (sys_.K @ U)).toarray()
+    P = U.T @ residual(sys_, u_old)
+    return Kc, P
+
+
+def solve_upper(Kc: np.ndarray, P: np.ndarray, rcond: float = 1e-13) -> np.ndarray:
+    """Minimum-norm solution of Eq. 8 after symmetric Jacobi scaling.
+
+    K_a is symmetric positive semidefinite and P lies in its range, so every
+    least-squares solution is exact and all give the same U a."""
+    d = np.diag(Kc).copy()
+    s = np.where(d > 0.0, 1.0 / np.sqrt(np.where(d > 0.0, d, 1.0)), 0.0)
+    Ks = Kc * s[:, None] * s[None, :]
+    w, V = sla.eigh(Ks)
+    keep = w > rcond * max(w.max(), 0.0)
+    y = V[:, keep] @ ((V[:, keep].T @ (P * s)) / w[keep])
+    return s * y
+
+
+@dataclasses.dataclass
+class Step:
+    """Every intermediate quantity of one outer iteration."""
+    r: np.ndarray            # residual at u_old
+    R1: float
+    R2: float
+    delta: np.ndarray        # relaxation increments (Eq. 13)
+    U: sp.csr_matrix         # modes
+    Kc: np.ndarray           # Eq. 6
+    P: np.ndarray            # Eq. 7
+    a: np.ndarray            # Eq. 8
+    u_new: np.ndarray        # Eq. 3
+
+
+class Method:
+    """Outer loop of the hierarchical solver with exact inner solves."""
+
+    def __init__(self, sys_: System, sets: Sets):
+        self.sys = sys_
+        self.sets = sets
+        self.local = LocalSolver(sys_, sets)
+
+    def step(self, u_old: np.ndarray) -> Step:
+        r = residual(self.sys, u_old)
+        R1, R2 = rel_residuals(self.sys, u_old)
+        delta = self.local.relax(r)
+        U = mode_matrix(self.sys, self.sets, delta)
+        Kc, P = upper_level(self.sys, U, u_old)
+        a = solve_upper(Kc, P)
+        return Step(r, R1, R2, delta, U, Kc, P, a, u_old + U @ a)
+
+    def run(self, tol: float, max_iters: int, u0: np.ndarray | None = None):
+        """Iterate from u0 (default: prescribed values, zero elsewhere) until
+        max(R1, R2) <= tol.  Returns (u, iterations, history), history rows
+        (R1, R2, energy) per iteration before its update."""
+        u = self.sys.u_c.copy() if u0 is None else u0.copy()
+        hist = []
+        for it in range(max_iters + 1):
+            R1, R2 = rel_residuals(self.sys, u)
+            hist.append((R1, R2, energy(self.sys, u)))
+            if max(R1, R2) <= tol or it == max_iters:
+                return u, it, hist
+            u = self.step(u).u_new
+        return u, max_iters, hist

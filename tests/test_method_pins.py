@@ -1,0 +1,116 @@
+"""Pins of the oracle's step-by-step method model against the properties the
+paper states or that follow from its equations:
+
+* the total energy (Eq. 2) never increases (section 2.1 end);
+* the upper-level solve makes the new residual orthogonal to every mode
+  (Eq. 5 set to zero);
+* one set with an exact local solve reaches the solution in one iteration
+  (the relaxation increment of Eq. 13 is then the exact correction);
+* the exact solution is a fixed point (zero relaxation, zero coefficients);
+* the upper-level matrix of Eq. 6 is symmetric positive semidefinite and the
+  force of Eq. 7 lies in its range;
+* the iterates do not depend on the representative node of Eq. 10 and 14;
+* the iteration converges to the plain solution of Eq. 1.
+
+Iteration counts are not pinned: the paper prints none.
+"""
+import numpy as np
+import pytest
+
+import oracle.method as om
+from oracle.solve import energy, rel_residuals, residual, solve, system_of
+from workloads import make_instance
+
+
+def _setup(nx, ny, E, seed=0, ea="lognormal", shift=(0.0, 0.0)):
+    inst = make_instance(nx, ny, seed=seed, ea=ea)
+    S = system_of(inst)
+    return S, om.Method(S, om.make_sets(nx, ny, E, rep_shift=shift))
+
+
+def test_energy_never_increases_ragged_sets():
+    S, m = _setup(50, 37, 16, seed=1)
+    u, it, hist = m.run(tol=0.0, max_iters=25)
+    Pi = [h[2] for h in hist]
+    assert all(Pi[k + 1] <= Pi[k] + 1e-13 * abs(Pi[k]) for k in range(len(Pi) - 1))
+    assert Pi[-1] < Pi[0]
+
+
+def test_galerkin_orthogonality_after_update():
+    S, m = _setup(40, 33, 16, seed=2)
+    u = S.u_c.copy()
+    for _ in range(3):
+        st = m.step(u)
+        g_old = st.U.T @ st.r
+        g_new = st.U.T @ residual(S, st.u_new)
+        assert np.linalg.norm(g_new) <= 1e-9 * np.linalg.norm(g_old)
+        u = st.u_new
+
+
+def test_single_set_converges_in_one_iteration():
+    S, m = _setup(20, 14, 32, seed=3)
+    assert m.sets.M == 1
+    st = m.step(S.u_c.copy())
+    assert max(rel_residuals(S, st.u_new)) <= 1e-12
+
+
+def test_exact_solution_is_fixed_point():
+    S, m = _setup(33, 20, 16, seed=4)
+    u = solve(S)
+    st = m.step(u)
+    assert np.linalg.norm(st.U @ st.a) <= 1e-10 * np.linalg.norm(u)
+    assert np.linalg.norm(st.delta) <= 1e-10 * np.linalg.norm(u)
+
+
+def test_upper_level_matrix_psd_and_force_consistent():
+    S, m = _setup(48, 40, 16, seed=5)
+    u = S.u_c.copy()
+    for _ in range(2):
+        st = m.step(u)
+        assert np.array_equal(st.Kc, st.Kc.T) or np.abs(st.Kc - st.Kc.T).max() <= 1e-14 * np.abs(st.Kc).max()
+        w, V = np.linalg.eigh(st.Kc)
+        assert w.min() >= -1e-11 * w.max()
+        null = V[:, w <= 1e-11 * w.max()]
+        assert np.linalg.norm(null.T @ st.P) <= 1e-9 * np.linalg.norm(st.P)
+        u = st.u_new
+
+
+def test_iterates_independent_of_representative_node():
+    S, m0 = _setup(45, 30, 16, seed=6)
+    _, m1 = _setup(45, 30, 16, seed=6, shift=(0.37, -1.3))
+    u0, _, _ = m0.run(tol=0.0, max_iters=4)
+    u1, _, _ = m1.run(tol=0.0, max_iters=4)
+    assert np.linalg.norm(u1 - u0) <= 1e-9 * np.linalg.norm(u0)
+
+
+def test_converges_to_plain_solution():
+    S, m = _setup(45, 37, 16, seed=7)
+    u, it, hist = m.run(tol=1e-10, max_iters=2000)
+    assert max(hist[-1][:2]) <= 1e-10
+    us = solve(S)
+    assert np.linalg.norm(u - us) <= 1e-8 * np.linalg.norm(us)
+
+
+def test_planted_sign_slip_in_force_is_caught(monkeypatch):
+    """A sign slip in Eq. 7 makes the update climb the energy."""
+    real = om.upper_level
+    monkeypatch.setattr(om, "upper_level", lambda S, U, u: (lambda kc, p: (kc, -p))(*real(S, U, u)))
+    with pytest.raises(AssertionError):
+        test_energy_never_increases_ragged_sets()
+
+
+def test_planted_wrong_gradient_mode_is_caught(monkeypatch):
+    """Losing the y-weighted relaxation mode of Eq. 14 (mode 9 a copy of
+    mode 8) leaves the new residual not orthogonal to the intended modes."""
+    real = om.mode_matrix
+
+    def no_eta(S, sets, delta):
+        U = real(S, sets, delta).tolil()
+        U[:, 8::om.Q] = U[:, 7::om.Q]
+        return U.tocsr()
+    S, m = _setup(40, 33, 16, seed=2)
+    st_good = m.step(S.u_c.copy())
+    monkeypatch.setattr(om, "mode_matrix", no_eta)
+    st_bad = m.step(S.u_c.copy())
+    g = st_good.U.T @ residual(S, st_bad.u_new)
+    assert np.linalg.norm(g) > 1e-6 * np.linalg.norm(st_good.U.T @ st_good.r)
