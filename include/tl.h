@@ -1,0 +1,166 @@
+/*
+ * tl.h -- C ABI of the MI355X hierarchical lattice solver.
+ *
+ * The library solves the linear equations K u = f of a 2-D triangle-lattice
+ * truss (Xu, Liu, Dong, "Scalable hierarchical parallel algorithm for the
+ * solution of super large-scale sparse linear equations"; problem statement
+ * Eq. 1, test problem section 3.1) with the paper's hierarchical iteration:
+ * per-set local relaxation with the neighbouring sets' displacements held
+ * fixed (section 2.2, Eq. 11-14), an upper-level ("master") equilibrium
+ * correction over q = 9 incremental modes per set (Eq. 3-10), and the global
+ * relative-residual stop test (Eq. 19).  Sets are E x E node tiles of the
+ * lattice's index grid, one GPU workgroup each.
+ *
+ * Lattice and layouts
+ *   Node (i, j), 0 <= i < nx, 0 <= j < ny, sits at (i + j/2, j*sqrt(3)/2).
+ *   Every node stores its three forward rods, length 1:
+ *     d = 0 : (i, j)-(i+1, j)   d = 1 : (i, j)-(i, j+1)   d = 2 : (i, j)-(i-1, j+1)
+ *   ea      : float  [3][ny][nx], axial stiffness EA of each rod (element
+ *             stiffness (EA/L) n n^T, L = 1); entries of rods that would
+ *             leave the lattice are ignored.
+ *   fixed   : uint8  [ny][nx], nonzero = node clamped (both DOFs prescribed).
+ *   u_fixed : double [ny][nx][2], prescribed displacement of clamped nodes.
+ *   f, u    : double [ny][nx][2], loads and displacements, C order, x then y.
+ *             Loads on clamped DOFs are ignored (they are support reactions).
+ *
+ * Ownership and threading
+ *   All pointers in a call are borrowed for the duration of the call only,
+ *   except that tl_submit borrows f_dev and u_dev until tl_poll has reported
+ *   the request finished.  Host arrays passed to tl_lattice_create are copied.
+ *   A lattice is immutable after creation; solves on one lattice from several
+ *   host threads are serialised internally.  Device pointers are hipMalloc'd
+ *   (or PyTorch) memory on the current device.
+ *
+ * Errors
+ *   Every call returns a tl_status; nothing aborts or throws across the ABI.
+ *   TL_E_NOCONV still writes the last iterate to u and fills the tl_info.
+ */
+#ifndef TL_H
+#define TL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tl_lattice tl_lattice;   /* opaque */
+typedef struct tl_server tl_server;     /* opaque */
+
+typedef enum {
+    TL_OK = 0,
+    TL_PENDING = 1,        /* tl_poll: request not finished yet               */
+    TL_E_INVAL = -1,       /* bad argument or descriptor                        */
+    TL_E_NOMEM = -2,       /* device allocation failed                          */
+    TL_E_NOCONV = -3,      /* max_iters reached before the tolerance            */
+    TL_E_DEVICE = -4,      /* HIP runtime error or a device-side abort          */
+    TL_E_BUDGET = -5,      /* request can never fit the server's HBM budget     */
+    TL_E_NONFINITE = -6    /* non-finite input or iterate                        */
+} tl_status;
+
+typedef enum {
+    TL_FP64 = 0,           /* every stage in float64                            */
+    TL_MIXED = 1           /* relaxation sweeps in float32 with per-set 2^-e
+                              scaling; residual, upper level, update in float64 */
+} tl_precision;
+
+typedef struct {
+    int32_t nx, ny;            /* nodes per side, each >= 2                      */
+    const float* ea;           /* [3][ny][nx]; NULL = every rod EA 1             */
+    const uint8_t* fixed;      /* [ny][nx]; NULL = nodes with i == 0 clamped      */
+    const double* u_fixed;     /* [ny][nx][2]; NULL = 0                          */
+    int32_t set_edge;          /* E in {16, 32, 64}; 0 = chosen by the library    */
+    int32_t ptrs_on_device;    /* 1: ea/fixed/u_fixed are device pointers         */
+} tl_lattice_desc;
+
+/* Optional per-solve diagnostics: device buffers (any may be NULL) that
+ * receive the quantities of the last completed outer iteration whose
+ * upper-level system was solved.  Sizes use M = number of sets. */
+typedef struct {
+    double* delta;        /* [ny][nx][2] relaxation increment (mode 7, Eq. 13), as stored */
+    double* kdiag;        /* [M][9][9]  diagonal upper-level blocks (Eq. 6)            */
+    double* koff;         /* [M][6][9][9] blocks to the 6 neighbouring sets (Eq. 6),
+                             neighbour order (+1,0) (0,+1) (-1,+1) (-1,0) (0,-1) (+1,-1) */
+    double* force;        /* [M][9] upper-level force (Eq. 7)                          */
+    double* coef;         /* [M][9] coefficients a (Eq. 8)                             */
+    double* residual_history; /* [max_iters + 1]: max(R1, R2) per outer iteration      */
+} tl_trace;
+
+typedef struct {
+    tl_precision precision;
+    double rtol;               /* stop when max(R1, R2) <= rtol (Eq. 19, both norms) */
+    int32_t max_iters;         /* outer iterations; 0 = library default             */
+    int32_t inner_iters;       /* relaxation PCG sweeps per set; 0 = default         */
+    int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default         */
+    double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default    */
+    int32_t warm_start;        /* 1: start from the free DOFs of u (else from 0)     */
+    tl_trace* trace;           /* NULL, or diagnostics to fill                       */
+} tl_opts;
+
+typedef struct {
+    tl_status status;
+    int32_t iters;             /* outer iterations performed                      */
+    double rel_res_l1;         /* Eq. 19 1-norm relative residual of the returned u */
+    double rel_res_l2;         /* 2-norm relative residual of the returned u        */
+    double energy;             /* total energy Pi of Eq. 2 at the returned u        */
+    double ms;                 /* device time of the solve                         */
+    int64_t coarse_iters;      /* upper-level PCG iterations summed over the solve  */
+} tl_info;
+
+/* Lattice geometry facts (for sizing buffers). */
+typedef struct {
+    int32_t nx, ny, set_edge, sets_x, sets_y, sets;
+    int64_t dof;               /* 2 * nx * ny                                      */
+    int64_t device_bytes;      /* device memory held by the lattice                */
+    int64_t solve_bytes[2];    /* per-solve state for TL_FP64, TL_MIXED            */
+} tl_lattice_facts;
+
+/* Validate the descriptor, copy the lattice to the device and precompute the
+ * constant part of the upper-level diagonal blocks (translation and
+ * gradient modes, Eq. 6 with Eq. 9-10).  Returns TL_E_INVAL without touching
+ * the device when nx or ny < 2, fewer than two nodes are clamped, set_edge is
+ * not 0/16/32/64, or an EA is negative or not finite (host-side input only). */
+tl_status tl_lattice_create(const tl_lattice_desc* desc, void* hip_stream, tl_lattice** out);
+void tl_lattice_destroy(tl_lattice* lat);
+tl_status tl_lattice_get_facts(const tl_lattice* lat, tl_lattice_facts* out);
+
+/* Solve K u = f for one load vector, stream-ordered on hip_stream (NULL =
+ * the null stream), returning after completion.  f_dev, u_dev: device
+ * double [ny][nx][2].  Returns TL_E_NONFINITE if f has a non-finite free
+ * entry or an iterate becomes non-finite. */
+tl_status tl_solve(tl_lattice* lat, const double* f_dev, double* u_dev,
+                   const tl_opts* opts, tl_info* info, void* hip_stream);
+
+/* Solve n independent lattices in fused launches: one tile kernel over the
+ * sets of all lattices, one upper-level kernel over all lattices.  infos[k]
+ * receives lattice k's result; the return value is TL_OK when every lattice
+ * converged, else the first failing status. */
+tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const* f_dev,
+                         double* const* u_dev, const tl_opts* opts, tl_info* infos,
+                         void* hip_stream);
+
+/* f <- f - K u (the residual of Eq. 7's bracket, float64) into r_dev (may be
+ * NULL), and out[0..2] = R1, R2 (Eq. 19) and the energy Pi (Eq. 2) of u. */
+tl_status tl_residual(tl_lattice* lat, const double* f_dev, const double* u_dev,
+                      double* r_dev, double out[3], void* hip_stream);
+
+/* Continuous-batching server.  Requests are admitted while the device state
+ * of all admitted requests fits hbm_budget_bytes and fewer than max_slots are
+ * admitted; a background worker advances all admitted requests together, one
+ * fused outer iteration at a time, and retires each as it converges. */
+tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, tl_server** out);
+tl_status tl_submit(tl_server* srv, tl_lattice* lat, const double* f_dev, double* u_dev,
+                    const tl_opts* opts, uint64_t* ticket);
+/* TL_PENDING until the request has finished; then its final status, with
+ * out filled (out->ms = submit-to-finish wall time). */
+tl_status tl_poll(tl_server* srv, uint64_t ticket, tl_info* out);
+/* Waits for every admitted and queued request, then frees the server. */
+void tl_server_destroy(tl_server* srv);
+
+const char* tl_strerror(tl_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TL_H */

@@ -1,0 +1,456 @@
+// Host runtime of the hierarchical lattice solver: the C ABI of include/tl.h.
+//
+// A solve enqueues, per outer iteration, the tile kernel (update, residual,
+// relaxation, set rows of the upper-level system), the boundary-block kernel
+// and the persistent upper-level kernel, which also evaluates the stop test
+// and raises a device flag.  The host only reads that flag between chunks of
+// iterations; kernels enqueued after the flag is raised return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "tl.h"
+#include "tl_internal.h"
+#include "tl_runtime.h"
+
+namespace tl {
+
+namespace {
+
+tl_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return TL_OK;
+  if (e == hipErrorOutOfMemory) return TL_E_NOMEM;
+  return TL_E_DEVICE;
+}
+
+#define TL_TRY(expr)                         \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return from_hip(e_); \
+  } while (0)
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v && *v ? std::atoi(v) : dflt;
+}
+
+}  // namespace
+
+int default_set_edge(int nx, int ny) {
+  const int side = std::max(nx, ny);
+  if (side <= 160) return 16;
+  if (side <= 2048) return 32;
+  return 64;
+}
+
+Geo make_geo(int nx, int ny, int E) {
+  Geo g;
+  g.nx = nx;
+  g.ny = ny;
+  g.pitch = ((nx + 2 + 15) / 16) * 16;
+  g.E = E;
+  g.mx = (nx + E - 1) / E;
+  g.my = (ny + E - 1) / E;
+  g.M = g.mx * g.my;
+  return g;
+}
+
+size_t padded_nodes(const Geo& g) { return (size_t)(g.ny + 2) * g.pitch; }
+
+size_t work_bytes(const Geo& g, bool mixed, int hist_cap) {
+  const size_t np = padded_nodes(g), M = g.M;
+  size_t b = 2 * np * sizeof(double2) + 2 * np * (mixed ? sizeof(float2) : sizeof(double2));
+  b += M * (Q + KROW + Q + NRM + NDIR * Q * Q + Q * Q + 45 + Q + 5 * Q) * sizeof(double);
+  b += 2 * COARSE_MAX_WG * NRM * sizeof(double) + (size_t)hist_cap * sizeof(double);
+  b += sizeof(Ctrl);
+  return b;
+}
+
+void Work::release() {
+  for (void* p : allocs) (void)hipFree(p);
+  allocs.clear();
+  if (ctrl_host) (void)hipHostFree(ctrl_host);
+  ctrl_host = nullptr;
+}
+
+tl_status Work::alloc(const Geo& g_, bool mixed_, int hist_cap_) {
+  g = g_;
+  mixed = mixed_;
+  hist_cap = hist_cap_;
+  const size_t np = padded_nodes(g), M = g.M;
+  auto get = [&](size_t bytes, void** p) -> hipError_t {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return e;
+    allocs.push_back(*p);
+    return hipMemset(*p, 0, bytes);
+  };
+  void* p;
+  for (int k = 0; k < 2; ++k) {
+    TL_TRY(get(np * sizeof(double2), &p)); u[k] = (double2*)p;
+    TL_TRY(get(np * (mixed ? sizeof(float2) : sizeof(double2)), &p)); d[k] = p;
+  }
+  TL_TRY(get(M * Q * sizeof(double), &p)); a = (double*)p;
+  TL_TRY(get(M * KROW * sizeof(double), &p)); krow = (double*)p;
+  TL_TRY(get(M * Q * sizeof(double), &p)); force = (double*)p;
+  TL_TRY(get(M * NRM * sizeof(double), &p)); nrm = (double*)p;
+  TL_TRY(get(M * NDIR * Q * Q * sizeof(double), &p)); off = (double*)p;
+  TL_TRY(get(M * Q * Q * sizeof(double), &p)); bdiag = (double*)p;
+  TL_TRY(get(M * 45 * sizeof(double), &p)); lfac = (double*)p;
+  TL_TRY(get(M * Q * sizeof(double), &p)); bscale = (double*)p;
+  TL_TRY(get(M * Q * sizeof(double), &p)); cr = (double*)p;
+  TL_TRY(get(M * Q * sizeof(double), &p)); cz = (double*)p;
+  TL_TRY(get(M * Q * sizeof(double), &p)); cp0 = (double*)p;
+  TL_TRY(get(M * Q * sizeof(double), &p)); cp1 = (double*)p;
+  TL_TRY(get(M * Q * sizeof(double), &p)); cq = (double*)p;
+  TL_TRY(get(2 * COARSE_MAX_WG * NRM * sizeof(double), &p)); red = (double*)p;
+  TL_TRY(get((size_t)hist_cap * sizeof(double), &p)); hist = (double*)p;
+  TL_TRY(get(sizeof(Ctrl), &p)); ctrl = (Ctrl*)p;
+  TL_TRY(hipHostMalloc((void**)&ctrl_host, sizeof(Ctrl), hipHostMallocDefault));
+  bytes = work_bytes(g, mixed, hist_cap);
+  return TL_OK;
+}
+
+int coarse_workgroups(int M) {
+  const int per = env_int("TL_COARSE_SETS_PER_WG", 16);
+  int n = (M + per - 1) / per;
+  return std::max(1, std::min(n, COARSE_MAX_WG));
+}
+
+void resolve_opts(const tl_opts* o, Opts* r) {
+  r->mixed = o && o->precision == TL_MIXED;
+  r->rtol = o && o->rtol > 0.0 ? o->rtol : 1e-8;
+  r->max_iters = o && o->max_iters > 0 ? o->max_iters : 20000;
+  r->inner = o && o->inner_iters > 0 ? o->inner_iters : 10;
+  r->coarse_iters = o && o->coarse_iters > 0 ? o->coarse_iters : 40;
+  r->coarse_rtol = o && o->coarse_rtol > 0.0 ? o->coarse_rtol : 1e-4;
+  r->warm = o ? o->warm_start : 0;
+  r->trace = o ? o->trace : nullptr;
+}
+
+// Enqueue outer iteration k of one solve.
+tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f, int k,
+                            hipStream_t st) {
+  TileArgs ta;
+  ta.u_in = w->u[k & 1];
+  ta.u_out = w->u[(k + 1) & 1];
+  ta.d_in = w->d[k & 1];
+  ta.d_out = w->d[(k + 1) & 1];
+  ta.a = w->a;
+  ta.f = (const double2*)f;
+  ta.krow = w->krow;
+  ta.force = w->force;
+  ta.nrm = w->nrm;
+  ta.ctrl = w->ctrl;
+  ta.inner_iters = o.inner;
+  TL_TRY(launch_tile(o.mixed, L->g, L->ea, L->mask, ta, st));
+  OffArgs oa;
+  oa.d = w->d[(k + 1) & 1];
+  oa.off = w->off;
+  oa.ctrl = w->ctrl;
+  TL_TRY(launch_offdiag(o.mixed, L->g, L->ea, L->mask, oa, st));
+  CoarseArgs ca;
+  ca.g1 = L->g1;
+  ca.krow = w->krow;
+  ca.force = w->force;
+  ca.nrm = w->nrm;
+  ca.off = w->off;
+  ca.bdiag = w->bdiag;
+  ca.lfac = w->lfac;
+  ca.bscale = w->bscale;
+  ca.a = w->a;
+  ca.cr = w->cr;
+  ca.cz = w->cz;
+  ca.cp0 = w->cp0;
+  ca.cp1 = w->cp1;
+  ca.cq = w->cq;
+  ca.red = w->red;
+  ca.hist = (o.trace && o.trace->residual_history) ? o.trace->residual_history : w->hist;
+  ca.tr_kdiag = o.trace ? o.trace->kdiag : nullptr;
+  ca.tr_koff = o.trace ? o.trace->koff : nullptr;
+  ca.tr_force = o.trace ? o.trace->force : nullptr;
+  ca.tr_coef = o.trace ? o.trace->coef : nullptr;
+  ca.ctrl = w->ctrl;
+  ca.iter = k;
+  ca.max_iters = o.max_iters;
+  ca.coarse_iters = o.coarse_iters;
+  ca.coarse_rtol = o.coarse_rtol;
+  ca.rtol = o.rtol;
+  ca.nwg = coarse_workgroups(L->g.M);
+  ca.spin_limit = 1u << 22;
+  TL_TRY(launch_coarse(L->g, ca, st));
+  return TL_OK;
+}
+
+tl_status certify(const tl_lattice* L, const double* f, const double* u, double* r,
+                  double out3[3], hipStream_t st) {
+  TL_TRY(launch_residual(L->g, L->ea, L->mask, (const double2*)f, (const double2*)u, (double2*)r,
+                         L->res_part, L->res_out, st));
+  TL_TRY(hipMemcpyAsync(L->out5_host, L->res_out, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+  TL_TRY(hipStreamSynchronize(st));
+  const double* o5 = L->out5_host;
+  out3[0] = o5[2] > 0.0 ? o5[0] / o5[2] : o5[0];
+  out3[1] = o5[3] > 0.0 ? std::sqrt(o5[1] / o5[3]) : std::sqrt(o5[1]);
+  out3[2] = o5[4];
+  return TL_OK;
+}
+
+tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, double* u,
+                    tl_info* info, hipStream_t st) {
+  hipEvent_t e0, e1;
+  TL_TRY(hipEventCreate(&e0));
+  TL_TRY(hipEventCreate(&e1));
+  TL_TRY(launch_init_state(L->g, L->mask, L->ufix, (const double2*)u, o.warm, w->u[0], w->u[1],
+                           w->d[0], w->d[1], o.mixed, w->a, w->ctrl, st));
+  TL_TRY(hipEventRecord(e0, st));
+  int k = 0, chunk = 4;
+  tl_status st_run = TL_OK;
+  for (;;) {
+    for (int c = 0; c < chunk && k <= o.max_iters; ++c, ++k) {
+      st_run = enqueue_iteration(L, w, o, f, k, st);
+      if (st_run != TL_OK) break;
+    }
+    if (st_run != TL_OK) break;
+    TL_TRY(hipMemcpyAsync(w->ctrl_host, w->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    TL_TRY(hipStreamSynchronize(st));
+    if (w->ctrl_host->err) { st_run = TL_E_DEVICE; break; }
+    if (w->ctrl_host->done) break;
+    if (k > o.max_iters) { st_run = TL_E_DEVICE; break; }
+    chunk = std::min(chunk * 2, 64);
+  }
+  TL_TRY(hipEventRecord(e1, st));
+  if (st_run != TL_OK) {
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st_run;
+  }
+  const Ctrl c = *w->ctrl_host;
+  const int kf = c.iters;
+  TL_TRY(launch_copy_out(L->g, w->u[(kf + 1) & 1], (double2*)u, st));
+  if (o.trace && o.trace->delta && kf >= 1)
+    TL_TRY(launch_copy_delta(o.mixed, L->g, w->d[kf & 1], (double2*)o.trace->delta, st));
+  TL_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  TL_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  double out3[3];
+  tl_status cs = certify(L, f, u, nullptr, out3, st);
+  if (cs != TL_OK) return cs;
+  if (info) {
+    info->status = (tl_status)c.status;
+    info->iters = kf;
+    info->rel_res_l1 = out3[0];
+    info->rel_res_l2 = out3[1];
+    info->energy = out3[2];
+    info->ms = ms;
+    info->coarse_iters = c.coarse_iters;
+  }
+  if (c.status == 0 && !(std::isfinite(out3[0]) && std::isfinite(out3[1]))) return TL_E_NONFINITE;
+  return (tl_status)c.status;
+}
+
+Work* lattice_work(tl_lattice* L, bool mixed, int hist_cap, tl_status* err) {
+  Work*& w = L->work[mixed ? 1 : 0];
+  if (w && w->hist_cap >= hist_cap) return w;
+  if (w) {
+    w->release();
+    delete w;
+    w = nullptr;
+  }
+  w = new (std::nothrow) Work();
+  if (!w) { *err = TL_E_NOMEM; return nullptr; }
+  tl_status s = w->alloc(L->g, mixed, hist_cap);
+  if (s != TL_OK) {
+    w->release();
+    delete w;
+    w = nullptr;
+    *err = s;
+    return nullptr;
+  }
+  return w;
+}
+
+}  // namespace tl
+
+using namespace tl;
+
+extern "C" {
+
+const char* tl_strerror(tl_status s) {
+  switch (s) {
+    case TL_OK: return "ok";
+    case TL_PENDING: return "pending";
+    case TL_E_INVAL: return "invalid argument";
+    case TL_E_NOMEM: return "device out of memory";
+    case TL_E_NOCONV: return "not converged within max_iters";
+    case TL_E_DEVICE: return "HIP runtime or device error";
+    case TL_E_BUDGET: return "request exceeds the HBM budget";
+    case TL_E_NONFINITE: return "non-finite input or iterate";
+  }
+  return "unknown status";
+}
+
+tl_status tl_lattice_create(const tl_lattice_desc* desc, void* hip_stream, tl_lattice** out) {
+  if (!desc || !out) return TL_E_INVAL;
+  *out = nullptr;
+  const int nx = desc->nx, ny = desc->ny;
+  if (nx < 2 || ny < 2) return TL_E_INVAL;
+  if ((long long)nx * ny > (1ll << 31)) return TL_E_INVAL;
+  int E = desc->set_edge;
+  if (E != 0 && E != 16 && E != 32 && E != 64) return TL_E_INVAL;
+  const size_t nn = (size_t)nx * ny;
+  if (!desc->ptrs_on_device) {
+    if (desc->ea) {
+      for (size_t n = 0; n < 3 * nn; ++n) {
+        const float v = desc->ea[n];
+        if (!(v >= 0.0f) || !std::isfinite(v)) return TL_E_INVAL;
+      }
+    }
+    size_t nfix = 0;
+    if (desc->fixed) {
+      for (size_t n = 0; n < nn; ++n) nfix += desc->fixed[n] != 0;
+    } else {
+      nfix = (size_t)ny;
+    }
+    if (nfix < 2) return TL_E_INVAL;
+    if (desc->u_fixed)
+      for (size_t n = 0; n < 2 * nn; ++n)
+        if (!std::isfinite(desc->u_fixed[n])) return TL_E_NONFINITE;
+  }
+  if (E == 0) E = default_set_edge(nx, ny);
+  hipStream_t st = (hipStream_t)hip_stream;
+  tl_lattice* L = new (std::nothrow) tl_lattice();
+  if (!L) return TL_E_NOMEM;
+  L->g = make_geo(nx, ny, E);
+  auto fail = [&](tl_status s) { tl_lattice_destroy(L); return s; };
+  if (hipGetDevice(&L->device) != hipSuccess) return fail(TL_E_DEVICE);
+  const size_t np = padded_nodes(L->g);
+  auto dalloc = [&](void** p, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) {
+      L->allocs.push_back(*p);
+      L->bytes += bytes;
+      e = hipMemset(*p, 0, bytes);
+    }
+    return e;
+  };
+  void* p;
+  hipError_t e;
+  if ((e = dalloc(&p, 3 * np * sizeof(float))) != hipSuccess) return fail(from_hip(e));
+  L->ea = (float*)p;
+  if ((e = dalloc(&p, np)) != hipSuccess) return fail(from_hip(e));
+  L->mask = (uint8_t*)p;
+  if ((e = dalloc(&p, (size_t)L->g.M * 36 * sizeof(double))) != hipSuccess) return fail(from_hip(e));
+  L->g1 = (double*)p;
+  int* stats;
+  if ((e = dalloc(&p, 2 * sizeof(int))) != hipSuccess) return fail(from_hip(e));
+  stats = (int*)p;
+  if ((e = dalloc(&p, residual_partials(L->g) * sizeof(double))) != hipSuccess) return fail(from_hip(e));
+  L->res_part = (double*)p;
+  if ((e = dalloc(&p, 5 * sizeof(double))) != hipSuccess) return fail(from_hip(e));
+  L->res_out = (double*)p;
+  if (hipHostMalloc((void**)&L->out5_host, 5 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return fail(TL_E_NOMEM);
+  // stage host inputs on the device
+  const float* ea_src = desc->ea;
+  const uint8_t* fx_src = desc->fixed;
+  void* tmp_ea = nullptr;
+  void* tmp_fx = nullptr;
+  if (!desc->ptrs_on_device) {
+    if (desc->ea) {
+      if (hipMalloc(&tmp_ea, 3 * nn * sizeof(float)) != hipSuccess) return fail(TL_E_NOMEM);
+      if (hipMemcpy(tmp_ea, desc->ea, 3 * nn * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(tmp_ea);
+        return fail(TL_E_DEVICE);
+      }
+      ea_src = (const float*)tmp_ea;
+    }
+    if (desc->fixed) {
+      if (hipMalloc(&tmp_fx, nn) != hipSuccess) { if (tmp_ea) (void)hipFree(tmp_ea); return fail(TL_E_NOMEM); }
+      if (hipMemcpy(tmp_fx, desc->fixed, nn, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(tmp_fx);
+        if (tmp_ea) (void)hipFree(tmp_ea);
+        return fail(TL_E_DEVICE);
+      }
+      fx_src = (const uint8_t*)tmp_fx;
+    }
+  }
+  e = launch_pad_copy_stats(L->g, ea_src, fx_src, ea_src == nullptr, fx_src == nullptr, L->ea,
+                            L->mask, stats, st);
+  int hs[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (tmp_ea) (void)hipFree(tmp_ea);
+  if (tmp_fx) (void)hipFree(tmp_fx);
+  if (e != hipSuccess) return fail(from_hip(e));
+  if (hs[0] != 0 || hs[1] < 2) return fail(TL_E_INVAL);
+  if (desc->u_fixed) {
+    if ((e = dalloc(&p, nn * sizeof(double2))) != hipSuccess) return fail(from_hip(e));
+    L->ufix = (double2*)p;
+    e = hipMemcpy(L->ufix, desc->u_fixed, nn * sizeof(double2),
+                  desc->ptrs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(from_hip(e));
+  }
+  e = launch_group1(L->g, L->ea, L->mask, L->g1, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(from_hip(e));
+  *out = L;
+  return TL_OK;
+}
+
+void tl_lattice_destroy(tl_lattice* L) {
+  if (!L) return;
+  for (int k = 0; k < 2; ++k)
+    if (L->work[k]) {
+      L->work[k]->release();
+      delete L->work[k];
+    }
+  for (void* p : L->allocs) (void)hipFree(p);
+  if (L->out5_host) (void)hipHostFree(L->out5_host);
+  delete L;
+}
+
+tl_status tl_lattice_get_facts(const tl_lattice* L, tl_lattice_facts* out) {
+  if (!L || !out) return TL_E_INVAL;
+  out->nx = L->g.nx;
+  out->ny = L->g.ny;
+  out->set_edge = L->g.E;
+  out->sets_x = L->g.mx;
+  out->sets_y = L->g.my;
+  out->sets = L->g.M;
+  out->dof = 2ll * L->g.nx * L->g.ny;
+  out->device_bytes = (int64_t)L->bytes;
+  out->solve_bytes[0] = (int64_t)work_bytes(L->g, false, 20001);
+  out->solve_bytes[1] = (int64_t)work_bytes(L->g, true, 20001);
+  return TL_OK;
+}
+
+tl_status tl_solve(tl_lattice* L, const double* f_dev, double* u_dev, const tl_opts* opts,
+                   tl_info* info, void* hip_stream) {
+  if (!L || !f_dev || !u_dev) return TL_E_INVAL;
+  Opts o;
+  resolve_opts(opts, &o);
+  if (!(o.rtol > 0.0) || o.max_iters < 0 || o.inner < 0) return TL_E_INVAL;
+  std::lock_guard<std::mutex> lock(L->mu);
+  tl_status err = TL_OK;
+  Work* w = lattice_work(L, o.mixed, o.max_iters + 1, &err);
+  if (!w) return err;
+  return run_solve(L, w, o, f_dev, u_dev, info, (hipStream_t)hip_stream);
+}
+
+tl_status tl_residual(tl_lattice* L, const double* f_dev, const double* u_dev, double* r_dev,
+                      double out[3], void* hip_stream) {
+  if (!L || !f_dev || !u_dev || !out) return TL_E_INVAL;
+  std::lock_guard<std::mutex> lock(L->mu);
+  return certify(L, f_dev, u_dev, r_dev, out, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"

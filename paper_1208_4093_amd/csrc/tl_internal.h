@@ -1,0 +1,134 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+//
+// Device layout of one lattice (nx x ny nodes, set edge E):
+//   * node arrays are padded with a one-node ring: node (i, j), -1 <= i <= nx,
+//     -1 <= j <= ny, lives at (j + 1) * pitch + (i + 1).  The ring is clamped
+//     (mask 1), carries zero rod stiffness and zero displacement, so stencil
+//     and halo loads never leave the allocation and need no bounds tests;
+//   * ea      : float  [3][ny + 2][pitch]   rod EA of the three forward rods;
+//   * mask    : uint8  [ny + 2][pitch]      1 = clamped (or ring);
+//   * u, delta: double2 / T2 [ny + 2][pitch], two of each (ping-pong);
+//   * per-set upper-level data, set id s = J * mx + I:
+//       g1 [M][36]   constant 6x6 block of the translation/gradient modes;
+//       krow [M][27] rows of modes 7-9 of the diagonal block (cols 1-9);
+//       force [M][9], norm partials [M][4];
+//       off [M][6][81] blocks to the six neighbouring sets;
+//       bdiag [M][81], lfac [M][45], bscale [M][9]  assembled block and its
+//       scaled, pivot-dropping Cholesky factor (block-Jacobi preconditioner).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tl {
+
+constexpr int Q = 9;            // modes per set (Eq. 9, 10, 13, 14)
+constexpr int NDIR = 6;         // neighbouring sets in the set grid
+constexpr int KROW = 27;        // 3 relaxation-mode rows x 9 columns
+constexpr int NRM = 4;          // sum|r|, sum r^2, sum|f|, sum f^2 (free DOFs)
+constexpr int TILE_OUT = KROW + Q + NRM;
+constexpr int COARSE_NT = 256;  // threads per upper-level workgroup
+constexpr int COARSE_MAX_WG = 256;
+
+// Set-grid neighbour offsets (dI, dJ); direction d and d + 3 are opposite.
+__host__ __device__ constexpr int nb_di(int d) { return d == 0 ? 1 : d == 2 ? -1 : d == 3 ? -1 : d == 5 ? 1 : 0; }
+__host__ __device__ constexpr int nb_dj(int d) { return d == 1 ? 1 : d == 2 ? 1 : d == 4 ? -1 : d == 5 ? -1 : 0; }
+
+struct Geo {
+  int nx, ny, pitch, E, mx, my, M;
+};
+
+// Device-side control block of one solve.
+struct Ctrl {
+  int done;          // 0 running, else 1 + status code offset (see host)
+  int status;        // tl_status of the finished solve
+  int iters;         // outer iteration at which the solve finished
+  int err;           // device-side abort (barrier time-out)
+  long long coarse_iters;
+  double r1, r2;     // relative residuals of the last checked iterate
+  unsigned bar_count, bar_gen;   // grid barrier of the upper-level kernel
+};
+
+template <typename T> struct V2;
+template <> struct V2<float> { using type = float2; };
+template <> struct V2<double> { using type = double2; };
+
+struct TileArgs {
+  const double2* u_in;
+  double2* u_out;
+  const void* d_in;      // T2 padded
+  void* d_out;           // T2 padded
+  const double* a;       // [M][9] coefficients of the previous upper-level solve
+  const double2* f;      // [ny][nx] loads (unpadded, caller's buffer)
+  double* krow;          // [M][27]
+  double* force;         // [M][9]
+  double* nrm;           // [M][4]
+  const Ctrl* ctrl;
+  int inner_iters;
+};
+
+struct CoarseArgs {
+  const double* g1;      // [M][36]
+  const double* krow;    // [M][27]
+  const double* force;   // [M][9]
+  const double* nrm;     // [M][4]
+  const double* off;     // [M][6][81]
+  double* bdiag;         // [M][81]
+  double* lfac;          // [M][45]
+  double* bscale;        // [M][9]
+  double* a;             // [M][9] solution (coefficients)
+  double* cr;            // [9M] residual
+  double* cz;            // [9M] preconditioned residual
+  double* cp0;           // [9M] search direction, ping
+  double* cp1;           // [9M] search direction, pong
+  double* cq;            // [9M] K_a p
+  double* red;           // [2][COARSE_MAX_WG][NRM] reduction slots
+  double* hist;          // [max_iters + 1] max(R1, R2) per outer iteration (may be null)
+  double* tr_kdiag;      // optional copies of the solved system (diagnostics)
+  double* tr_koff;
+  double* tr_force;
+  double* tr_coef;
+  Ctrl* ctrl;
+  int iter;              // outer iteration index
+  int max_iters;
+  int coarse_iters;
+  double coarse_rtol;
+  double rtol;
+  int nwg;
+  unsigned spin_limit;
+};
+
+struct OffArgs {
+  const void* d;         // T2 padded relaxation increments of this iteration
+  double* off;           // [M][6][81]
+  const Ctrl* ctrl;
+};
+
+// Launchers (tl_kernels.hip).  All are asynchronous on `stream`.
+hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
+                       const TileArgs& a, hipStream_t stream);
+hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
+                          const OffArgs& a, hipStream_t stream);
+hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream);
+hipError_t launch_group1(const Geo& g, const float* ea, const uint8_t* mask, double* g1,
+                         hipStream_t stream);
+hipError_t launch_init_state(const Geo& g, const uint8_t* mask, const double2* u_fixed,
+                             const double2* u_user, int warm, double2* u0,
+                             double2* u1, void* d0, void* d1, bool mixed, double* a,
+                             Ctrl* ctrl, hipStream_t stream);
+hipError_t launch_copy_out(const Geo& g, const double2* u_pad, double2* u_user,
+                           hipStream_t stream);
+hipError_t launch_copy_delta(bool mixed, const Geo& g, const void* d_pad, double2* out,
+                             hipStream_t stream);
+// r = f - K u (unpadded f, u, r), and partial sums for R1, R2 and the energy.
+hipError_t launch_residual(const Geo& g, const float* ea, const uint8_t* mask,
+                           const double2* f, const double2* u, double2* r,
+                           double* partials, double* out5, hipStream_t stream);
+size_t residual_partials(const Geo& g);
+// Pad and copy the lattice description; stats[0] += non-finite or negative
+// EA count, stats[1] += clamped node count.
+hipError_t launch_pad_copy_stats(const Geo& g, const float* ea_user, const uint8_t* fixed_user,
+                                 int ea_default, int fixed_default, float* ea, uint8_t* mask,
+                                 int* stats, hipStream_t stream);
+
+}  // namespace tl

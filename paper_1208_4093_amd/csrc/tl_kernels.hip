@@ -1,0 +1,1035 @@
+// HIP kernels of the hierarchical lattice solver (gfx950).
+//
+// One outer iteration of the method (Xu, Liu, Dong, section 2) is three
+// launches:
+//   k_tile    one workgroup per set (E x E node tile): applies the previous
+//             upper-level correction (Eq. 3) to the tile and a one-node halo,
+//             forms the float64 residual f - K u with the matrix-free rod
+//             stencil, relaxes the set with its neighbours held fixed
+//             (Eq. 11-13; preconditioned CG sweeps in LDS), and accumulates
+//             the set's rows of the upper-level matrix for the relaxation
+//             modes (Eq. 6, 13, 14) and its upper-level force (Eq. 7);
+//   k_offdiag one workgroup per set: upper-level blocks between neighbouring
+//             sets from the rods the set boundaries cut (Eq. 6);
+//   k_coarse  persistent grid: global residual test (Eq. 19), then the
+//             upper-level system (Eq. 8) by block-Jacobi PCG.
+// Plus create-time, set-up and certification kernels.
+#include "tl_internal.h"
+
+#include <math.h>
+
+namespace tl {
+
+namespace {
+
+constexpr double kS3 = 0.86602540378443864676;   // sqrt(3)/2, y-step of a lattice row
+
+__device__ __forceinline__ size_t pidx(const Geo& g, int i, int j) {
+  return (size_t)(j + 1) * g.pitch + (size_t)(i + 1);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous run of tiles so that halo rows shared by neighbouring tiles
+// stay in one L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  constexpr int X = 8;
+  const int xcd = b % X, k = b / X, per = nb / X, rem = nb % X;
+  return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
+
+// Normalised coordinates of node (i, j) about the centre of its set tile
+// [i0, i0 + tw) x [j0, j0 + th): xi = (x - xc) / (E/2), eta = (y - yc) / (E/2)
+// with x = i + j/2, y = j*sqrt(3)/2 (representative node = tile centroid).
+__device__ __forceinline__ void set_coords(int i, int j, int i0, int j0, int tw, int th,
+                                           double inv_hs, double& xi, double& eta) {
+  const double ic = i0 + 0.5 * (tw - 1), jc = j0 + 0.5 * (th - 1);
+  xi = ((i - ic) + 0.5 * (j - jc)) * inv_hs;
+  eta = ((j - jc) * kS3) * inv_hs;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Workgroup sum; every thread gets the same (bitwise) value.  `slot` holds
+// one entry per wave and must not be reused before the next barrier.
+template <int NW, typename T>
+__device__ __forceinline__ T block_sum(T v, double* slot) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = (double)v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += slot[w];
+  return (T)s;
+}
+
+template <typename T> __device__ __forceinline__ typename V2<T>::type mk2(T x, T y);
+template <> __device__ __forceinline__ float2 mk2<float>(float x, float y) { return make_float2(x, y); }
+template <> __device__ __forceinline__ double2 mk2<double>(double x, double y) { return make_double2(x, y); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Tile kernel: update + residual + local relaxation + set's upper-level rows.
+// ---------------------------------------------------------------------------
+template <typename T, int E, int NT>
+__global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea,
+                                             const uint8_t* __restrict__ mask, TileArgs A) {
+  using T2 = typename V2<T>::type;
+  constexpr int NPT = E * E / NT;
+  constexpr int W = E + 2;
+  constexpr int NW = NT / 64;
+  static_assert(E * E % NT == 0, "tile must split evenly over the workgroup");
+  __shared__ double2 su[W * W];                 // u over tile + halo, then T2 p / delta
+  __shared__ double sa[9][Q];                   // coefficients of the 3x3 set neighbourhood
+  __shared__ double sred[3][NW];
+  __shared__ double sacc[NW][KROW + 3];
+  __shared__ double sfin[11];
+  T2* sp = reinterpret_cast<T2*>(su);
+
+  if (A.ctrl->done) return;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int I = tile % g.mx, J = tile / g.mx;
+  const int i0 = I * E, j0 = J * E;
+  const int tw = min(E, g.nx - i0), th = min(E, g.ny - j0);
+  const int t = threadIdx.x;
+  const size_t plane = (size_t)(g.ny + 2) * g.pitch;
+  const double inv_hs = 2.0 / E;
+
+  if (t < 81) {
+    const int s = t / Q, m = t % Q;
+    const int I2 = I + (s % 3) - 1, J2 = J + (s / 3) - 1;
+    sa[s][m] = (I2 >= 0 && I2 < g.mx && J2 >= 0 && J2 < g.my)
+                   ? A.a[(size_t)(J2 * g.mx + I2) * Q + m] : 0.0;
+  }
+  __syncthreads();
+
+  // 1. u_new = u_old + sum_m a_m u_hat_m (Eq. 3) on the tile and its halo.
+  {
+    const T2* din = reinterpret_cast<const T2*>(A.d_in);
+    const int rw = tw + 2, rn = (tw + 2) * (th + 2);
+    for (int idx = t; idx < rn; idx += NT) {
+      const int ri = idx % rw, rj = idx / rw;
+      const int gi = i0 - 1 + ri, gj = j0 - 1 + rj;
+      const size_t p = pidx(g, gi, gj);
+      double2 u = A.u_in[p];
+      if (!mask[p]) {
+        const int dI = ri == 0 ? -1 : (ri == tw + 1 ? 1 : 0);
+        const int dJ = rj == 0 ? -1 : (rj == th + 1 ? 1 : 0);
+        const int oi0 = (I + dI) * E, oj0 = (J + dJ) * E;
+        double xi, eta;
+        set_coords(gi, gj, oi0, oj0, min(E, g.nx - oi0), min(E, g.ny - oj0), inv_hs, xi, eta);
+        const double* c = sa[(dJ + 1) * 3 + (dI + 1)];
+        const T2 dl = din[p];
+        const double w = c[6] + c[7] * xi + c[8] * eta;
+        u.x += c[0] + c[2] * xi + c[3] * eta + w * (double)dl.x;
+        u.y += c[1] + c[4] * xi + c[5] * eta + w * (double)dl.y;
+      }
+      su[rj * W + ri] = u;
+      if (ri >= 1 && ri <= tw && rj >= 1 && rj <= th) A.u_out[p] = u;
+    }
+  }
+  __syncthreads();
+
+  // 2. residual r = f - K u (float64) and the per-node relaxation operator.
+  float kk[NPT][6];
+  double2 r[NPT];
+  T dxx[NPT], dxy[NPT], dyy[NPT], ixx[NPT], ixy[NPT], iyy[NPT];
+  bool act[NPT];
+  double part[10];   // P1..P6, sum|r|, sum r^2, sum|f|, sum f^2
+#pragma unroll
+  for (int v = 0; v < 10; ++v) part[v] = 0.0;
+  double rmax = 0.0;
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int n = t + k * NT, li = n % E, lj = n / E;
+    const bool inside = li < tw && lj < th;
+    act[k] = false;
+    r[k] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < 6; ++b) kk[k][b] = 0.f;
+    dxx[k] = dxy[k] = dyy[k] = ixx[k] = ixy[k] = iyy[k] = (T)0;
+    if (!inside) continue;
+    const int gi = i0 + li, gj = j0 + lj;
+    const size_t p = pidx(g, gi, gj);
+    if (mask[p]) continue;
+    act[k] = true;
+    kk[k][0] = ea[p];
+    kk[k][1] = ea[plane + p];
+    kk[k][2] = ea[2 * plane + p];
+    kk[k][3] = ea[p - 1];
+    kk[k][4] = ea[plane + p - g.pitch];
+    kk[k][5] = ea[2 * plane + p - g.pitch + 1];
+    const int c = (lj + 1) * W + (li + 1);
+    const double2 ua = su[c];
+    double kx = 0.0, ky = 0.0;
+    auto rod = [&](float kb, double nx_, double ny_, double2 ub) {
+      const double s = (double)kb * (nx_ * (ua.x - ub.x) + ny_ * (ua.y - ub.y));
+      kx += s * nx_;
+      ky += s * ny_;
+    };
+    rod(kk[k][0], 1.0, 0.0, su[c + 1]);
+    rod(kk[k][1], 0.5, kS3, su[c + W]);
+    rod(kk[k][2], -0.5, kS3, su[c + W - 1]);
+    rod(kk[k][3], 1.0, 0.0, su[c - 1]);
+    rod(kk[k][4], 0.5, kS3, su[c - W]);
+    rod(kk[k][5], -0.5, kS3, su[c - W + 1]);
+    const double2 fv = A.f[(size_t)gj * g.nx + gi];
+    const double rx = fv.x - kx, ry = fv.y - ky;
+    r[k] = make_double2(rx, ry);
+    double xi, eta;
+    set_coords(gi, gj, i0, j0, tw, th, inv_hs, xi, eta);
+    part[0] += rx;
+    part[1] += ry;
+    part[2] += xi * rx;
+    part[3] += eta * rx;
+    part[4] += xi * ry;
+    part[5] += eta * ry;
+    part[6] += fabs(rx) + fabs(ry);
+    part[7] += rx * rx + ry * ry;
+    part[8] += fabs(fv.x) + fabs(fv.y);
+    part[9] += fv.x * fv.x + fv.y * fv.y;
+    rmax = fmax(rmax, fmax(fabs(rx), fabs(ry)));
+    // diagonal 2x2 block of k^Inner: sum over all six rods of k n n^T
+    const double ka = (double)kk[k][0] + kk[k][3];
+    const double kb = (double)kk[k][1] + kk[k][4];
+    const double kc = (double)kk[k][2] + kk[k][5];
+    const double Dxx = ka + 0.25 * (kb + kc), Dyy = 0.75 * (kb + kc), Dxy = 0.5 * kS3 * (kb - kc);
+    const double det = Dxx * Dyy - Dxy * Dxy;
+    dxx[k] = (T)Dxx; dxy[k] = (T)Dxy; dyy[k] = (T)Dyy;
+    ixx[k] = (T)(Dyy / det); ixy[k] = (T)(-Dxy / det); iyy[k] = (T)(Dxx / det);
+  }
+  // workgroup reduction of the 10 partials and the max |r|
+  {
+#pragma unroll
+    for (int v = 0; v < 10; ++v) part[v] = wave_sum(part[v]);
+    rmax = wave_max(rmax);
+    if ((t & 63) == 0) {
+#pragma unroll
+      for (int v = 0; v < 10; ++v) sacc[t >> 6][v] = part[v];
+      sacc[t >> 6][10] = rmax;
+    }
+    __syncthreads();   // also: every read of su as u is done
+    if (t < 11) {
+      double s = 0.0;
+      for (int w = 0; w < NW; ++w) s = t == 10 ? fmax(s, sacc[w][10]) : s + sacc[w][t];
+      sfin[t] = s;
+    }
+    // zero the relaxation buffer (tile, halo ring and inactive nodes)
+    for (int idx = t; idx < W * W; idx += NT) sp[idx] = mk2<T>((T)0, (T)0);
+    __syncthreads();
+  }
+  if (t < 6) A.force[(size_t)tile * Q + t] = sfin[t];
+  if (t >= 6 && t < 10) A.nrm[(size_t)tile * NRM + (t - 6)] = sfin[t];
+
+  // 3. local relaxation: k^Inner delta = r on the set's free DOFs, neighbour
+  //    sets held fixed (Eq. 12 minus k^Inner u_old), by block-Jacobi PCG.
+  //    Float32 form: r is scaled by 2^-e (e from max|r|) before rounding.
+  const double rm = sfin[10];
+  const double scl = (sizeof(T) == 4 && rm > 0.0 && isfinite(rm)) ? ldexp(1.0, -ilogb(rm)) : 1.0;
+  T2 x[NPT], rr[NPT], pp[NPT], zz[NPT], qq[NPT];
+  double rz_part = 0.0;
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    x[k] = mk2<T>((T)0, (T)0);
+    rr[k] = mk2<T>((T)(r[k].x * scl), (T)(r[k].y * scl));
+    zz[k] = mk2<T>(ixx[k] * rr[k].x + ixy[k] * rr[k].y, ixy[k] * rr[k].x + iyy[k] * rr[k].y);
+    pp[k] = zz[k];
+    rz_part += (double)(rr[k].x * zz[k].x + rr[k].y * zz[k].y);
+  }
+  double rz = block_sum<NW>(rz_part, sred[0]);
+  for (int it = 0; it < A.inner_iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      if (!act[k]) continue;
+      const int n = t + k * NT;
+      sp[(n / E + 1) * W + (n % E + 1)] = pp[k];
+    }
+    __syncthreads();
+    double pq_part = 0.0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      if (!act[k]) { qq[k] = mk2<T>((T)0, (T)0); continue; }
+      const int n = t + k * NT;
+      const int c = (n / E + 1) * W + (n % E + 1);
+      const T2 pa = pp[k];
+      T qx = dxx[k] * pa.x + dxy[k] * pa.y;
+      T qy = dxy[k] * pa.x + dyy[k] * pa.y;
+      T2 pb; T s;
+      pb = sp[c + 1];     s = (T)kk[k][0] * pb.x;                                qx -= s;
+      pb = sp[c - 1];     s = (T)kk[k][3] * pb.x;                                qx -= s;
+      pb = sp[c + W];     s = (T)kk[k][1] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
+      pb = sp[c - W];     s = (T)kk[k][4] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
+      pb = sp[c + W - 1]; s = (T)kk[k][2] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+      pb = sp[c - W + 1]; s = (T)kk[k][5] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+      qq[k] = mk2<T>(qx, qy);
+      pq_part += (double)(pa.x * qx + pa.y * qy);
+    }
+    const double pq = block_sum<NW>(pq_part, sred[1]);
+    const T alpha = pq > 0.0 ? (T)(rz / pq) : (T)0;
+    double rzn_part = 0.0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      x[k].x += alpha * pp[k].x;  x[k].y += alpha * pp[k].y;
+      rr[k].x -= alpha * qq[k].x; rr[k].y -= alpha * qq[k].y;
+      zz[k] = mk2<T>(ixx[k] * rr[k].x + ixy[k] * rr[k].y, ixy[k] * rr[k].x + iyy[k] * rr[k].y);
+      rzn_part += (double)(rr[k].x * zz[k].x + rr[k].y * zz[k].y);
+    }
+    const double rzn = block_sum<NW>(rzn_part, sred[it & 1 ? 0 : 2]);
+    const T beta = rz > 0.0 ? (T)(rzn / rz) : (T)0;
+    rz = rzn;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      pp[k].x = zz[k].x + beta * pp[k].x;
+      pp[k].y = zz[k].y + beta * pp[k].y;
+    }
+  }
+
+  // 4. store the relaxation increment (mode 7 as stored, scaled in float32)
+  {
+    T2* dout = reinterpret_cast<T2*>(A.d_out);
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int n = t + k * NT, li = n % E, lj = n / E;
+      if (li < tw && lj < th) {
+        const T2 d = act[k] ? x[k] : mk2<T>((T)0, (T)0);
+        dout[pidx(g, i0 + li, j0 + lj)] = d;
+        if (act[k]) sp[(lj + 1) * W + (li + 1)] = d;
+      }
+    }
+  }
+  __syncthreads();
+
+  // 5. rows 7-9 of the set's diagonal upper-level block, K[m][l] =
+  //    u_hat_m . k^Inner u_hat_l for l in {delta, xi*delta, eta*delta} (Eq. 6),
+  //    and P_7..9 = u_hat_l . r (Eq. 7), all in float64.
+  double acc[KROW + 3];
+#pragma unroll
+  for (int v = 0; v < KROW + 3; ++v) acc[v] = 0.0;
+  const double dxi[6] = {inv_hs, -inv_hs, 0.5 * inv_hs, -0.5 * inv_hs, -0.5 * inv_hs, 0.5 * inv_hs};
+  const double deta[6] = {0.0, 0.0, kS3 * inv_hs, -kS3 * inv_hs, kS3 * inv_hs, -kS3 * inv_hs};
+  const double nvx[6] = {1.0, 1.0, 0.5, 0.5, -0.5, -0.5};
+  const double nvy[6] = {0.0, 0.0, kS3, kS3, kS3, kS3};
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    if (!act[k]) continue;
+    const int n = t + k * NT, li = n % E, lj = n / E;
+    const int c = (lj + 1) * W + (li + 1);
+    const int off[6] = {1, -1, W, -W, W - 1, -W + 1};
+    const int kidx[6] = {0, 3, 1, 4, 2, 5};
+    double xi, eta;
+    set_coords(i0 + li, j0 + lj, i0, j0, tw, th, inv_hs, xi, eta);
+    const double dax = (double)x[k].x, day = (double)x[k].y;
+    const double ka = (double)kk[k][0] + kk[k][3];
+    const double kb = (double)kk[k][1] + kk[k][4];
+    const double kc = (double)kk[k][2] + kk[k][5];
+    const double Dxx = ka + 0.25 * (kb + kc), Dyy = 0.75 * (kb + kc), Dxy = 0.5 * kS3 * (kb - kc);
+    const double Ddx = Dxx * dax + Dxy * day, Ddy = Dxy * dax + Dyy * day;
+    double w7x = Ddx, w7y = Ddy, w8x = xi * Ddx, w8y = xi * Ddy, w9x = eta * Ddx, w9y = eta * Ddy;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const T2 db = sp[c + off[b]];
+      const double s7 = (double)kk[k][kidx[b]] * (nvx[b] * (double)db.x + nvy[b] * (double)db.y);
+      const double s8 = s7 * (xi + dxi[b]);
+      const double s9 = s7 * (eta + deta[b]);
+      w7x -= s7 * nvx[b]; w7y -= s7 * nvy[b];
+      w8x -= s8 * nvx[b]; w8y -= s8 * nvy[b];
+      w9x -= s9 * nvx[b]; w9y -= s9 * nvy[b];
+    }
+    const double wx[3] = {w7x, w8x, w9x}, wy[3] = {w7y, w8y, w9y};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double dw = dax * wx[q] + day * wy[q];
+      acc[q * 9 + 0] += wx[q];
+      acc[q * 9 + 1] += wy[q];
+      acc[q * 9 + 2] += xi * wx[q];
+      acc[q * 9 + 3] += eta * wx[q];
+      acc[q * 9 + 4] += xi * wy[q];
+      acc[q * 9 + 5] += eta * wy[q];
+      acc[q * 9 + 6] += dw;
+      acc[q * 9 + 7] += xi * dw;
+      acc[q * 9 + 8] += eta * dw;
+    }
+    const double dr = dax * r[k].x + day * r[k].y;
+    acc[KROW + 0] += dr;
+    acc[KROW + 1] += xi * dr;
+    acc[KROW + 2] += eta * dr;
+  }
+#pragma unroll
+  for (int v = 0; v < KROW + 3; ++v) acc[v] = wave_sum(acc[v]);
+  if ((t & 63) == 0) {
+#pragma unroll
+    for (int v = 0; v < KROW + 3; ++v) sacc[t >> 6][v] = acc[v];
+  }
+  __syncthreads();
+  if (t < KROW + 3) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += sacc[w][t];
+    if (t < KROW) A.krow[(size_t)tile * KROW + t] = s;
+    else A.force[(size_t)tile * Q + 6 + (t - KROW)] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Upper-level blocks between neighbouring sets, from the rods their common
+// boundary cuts: K[Im][Jl] = -sum_rods k (n . u_hat_m^I(a)) (n . u_hat_l^J(c)).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_offdiag(Geo g, const float* __restrict__ ea,
+                                                 const uint8_t* __restrict__ mask, OffArgs A) {
+  using T2 = typename V2<T>::type;
+  constexpr int MAXB = 2 * 64;
+  __shared__ double G[MAXB][Q];
+  __shared__ double H[MAXB][Q];
+  if (A.ctrl->done) return;
+  const int s = blockIdx.x, I = s % g.mx, J = s / g.mx;
+  const int E = g.E;
+  const int i0 = I * E, j0 = J * E, tw = min(E, g.nx - i0), th = min(E, g.ny - j0);
+  const size_t plane = (size_t)(g.ny + 2) * g.pitch;
+  const double inv_hs = 2.0 / E;
+  const T2* d = reinterpret_cast<const T2*>(A.d);
+  const int t = threadIdx.x;
+
+  for (int dir = 0; dir < 3; ++dir) {
+    const int I2 = I + nb_di(dir), J2 = J + nb_dj(dir);
+    if (I2 < 0 || I2 >= g.mx || J2 < 0 || J2 >= g.my) continue;
+    const int oi0 = I2 * E, oj0 = J2 * E, otw = min(E, g.nx - oi0), oth = min(E, g.ny - oj0);
+    const int nb = dir == 0 ? 2 * th - 1 : dir == 1 ? 2 * tw - 1 : 1;
+    for (int b = t; b < nb; b += blockDim.x) {
+      int ai, aj, ci, cj, plane_id;
+      size_t kp;
+      double nx_, ny_;
+      if (dir == 0) {
+        if (b < th) { ai = i0 + tw - 1; aj = j0 + b; ci = ai + 1; cj = aj; nx_ = 1.0; ny_ = 0.0; plane_id = 0; kp = pidx(g, ai, aj); }
+        else { const int rr = b - th; ci = i0 + tw; cj = j0 + rr; ai = ci - 1; aj = cj + 1; nx_ = -0.5; ny_ = kS3; plane_id = 2; kp = pidx(g, ci, cj); }
+      } else if (dir == 1) {
+        if (b < tw) { ai = i0 + b; aj = j0 + th - 1; ci = ai; cj = aj + 1; nx_ = 0.5; ny_ = kS3; plane_id = 1; kp = pidx(g, ai, aj); }
+        else { const int rr = b - tw + 1; ai = i0 + rr; aj = j0 + th - 1; ci = ai - 1; cj = aj + 1; nx_ = -0.5; ny_ = kS3; plane_id = 2; kp = pidx(g, ai, aj); }
+      } else {
+        ai = i0; aj = j0 + th - 1; ci = ai - 1; cj = aj + 1; nx_ = -0.5; ny_ = kS3; plane_id = 2; kp = pidx(g, ai, aj);
+      }
+      const double kr = (double)ea[plane_id * plane + kp];
+      const size_t pa = pidx(g, ai, aj), pc = pidx(g, ci, cj);
+      double xa, ya, xc, yc;
+      set_coords(ai, aj, i0, j0, tw, th, inv_hs, xa, ya);
+      set_coords(ci, cj, oi0, oj0, otw, oth, inv_hs, xc, yc);
+      const bool fa = mask[pa] == 0, fc = mask[pc] == 0;
+      const T2 da = d[pa], dc = d[pc];
+      const double nda = nx_ * (double)da.x + ny_ * (double)da.y;
+      const double ndc = nx_ * (double)dc.x + ny_ * (double)dc.y;
+      const double ga[Q] = {nx_, ny_, xa * nx_, ya * nx_, xa * ny_, ya * ny_, nda, xa * nda, ya * nda};
+      const double gc[Q] = {nx_, ny_, xc * nx_, yc * nx_, xc * ny_, yc * ny_, ndc, xc * ndc, yc * ndc};
+#pragma unroll
+      for (int m = 0; m < Q; ++m) {
+        G[b][m] = fa ? kr * ga[m] : 0.0;
+        H[b][m] = fc ? gc[m] : 0.0;
+      }
+    }
+    __syncthreads();
+    if (t < Q * Q) {
+      const int m = t / Q, l = t % Q;
+      double acc = 0.0;
+      for (int b = 0; b < nb; ++b) acc -= G[b][m] * H[b][l];
+      const int s2 = J2 * g.mx + I2;
+      A.off[((size_t)s * NDIR + dir) * Q * Q + m * Q + l] = acc;
+      A.off[((size_t)s2 * NDIR + dir + 3) * Q * Q + l * Q + m] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Upper level: stop test of Eq. 19 and block-Jacobi PCG on Eq. 8.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Grid-wide barrier over the co-resident workgroups of k_coarse.  Bounded:
+// a workgroup that waits longer than spin_limit polls flags an error, and
+// every later barrier then returns false at once, so the grid always drains.
+__device__ bool grid_sync(Ctrl* c, int nwg, unsigned spin_limit) {
+  __shared__ int ok;
+  __threadfence();
+  __syncthreads();
+  if (nwg == 1) return true;
+  if (threadIdx.x == 0) {
+    int good = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    if (good) {
+      const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned arrived =
+          __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (arrived == (unsigned)nwg - 1u) {
+        __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        unsigned n = 0;
+        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          if (++n > spin_limit ||
+              __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            __hip_atomic_store(&c->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            good = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    ok = good;
+  }
+  __syncthreads();
+  __threadfence();
+  return ok != 0;
+}
+
+// Sum over the grid; identical in every thread of every workgroup.
+__device__ bool grid_sum(double v, double* red, int slot, Ctrl* c, int nwg, unsigned spin,
+                         double* sslot, double& out) {
+  v = block_sum<COARSE_NT / 64>(v, sslot);
+  if (threadIdx.x == 0) red[(size_t)slot * COARSE_MAX_WG * NRM + blockIdx.x * NRM] = v;
+  if (!grid_sync(c, nwg, spin)) return false;
+  double s = 0.0;
+  for (int w = 0; w < nwg; ++w) s += red[(size_t)slot * COARSE_MAX_WG * NRM + w * NRM];
+  out = s;
+  return true;
+}
+
+__device__ __forceinline__ int lpk(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// z = B^+ r for one set: scaled factor with dropped (dependent) modes zero.
+__device__ void block_apply(const double* __restrict__ L, const double* __restrict__ sc,
+                            const double* r, double* z) {
+  double y[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double v = sc[k] * r[k];
+#pragma unroll
+    for (int j = 0; j < k; ++j) v -= L[lpk(k, j)] * y[j];
+    const double dkk = L[lpk(k, k)];
+    y[k] = dkk > 0.0 ? v / dkk : 0.0;
+  }
+#pragma unroll
+  for (int k = Q - 1; k >= 0; --k) {
+    double v = y[k];
+#pragma unroll
+    for (int i = k + 1; i < Q; ++i) v -= L[lpk(i, k)] * z[i];
+    const double dkk = L[lpk(k, k)];
+    z[k] = dkk > 0.0 ? v / dkk : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) z[k] *= sc[k];
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
+  __shared__ double sslot[COARSE_NT / 64];
+  Ctrl* ctrl = A.ctrl;
+  if (ctrl->done) return;
+  const int w = blockIdx.x, nwg = gridDim.x, t = threadIdx.x;
+  const int M = g.M;
+  const int spw = (M + nwg - 1) / nwg;
+  const int s0 = min(M, w * spw), s1 = min(M, s0 + spw), ns = s1 - s0;
+  const unsigned spin = A.spin_limit;
+
+  // --- global residual (Eq. 19, both norms) and stop test
+  double nv[NRM] = {0.0, 0.0, 0.0, 0.0};
+  for (int s = s0 + t; s < s1; s += COARSE_NT) {
+#pragma unroll
+    for (int v = 0; v < NRM; ++v) nv[v] += A.nrm[(size_t)s * NRM + v];
+  }
+  double tot[NRM];
+  {
+#pragma unroll
+    for (int v = 0; v < NRM; ++v) {
+      const double bs = block_sum<COARSE_NT / 64>(nv[v], sslot);
+      if (t == 0) A.red[(size_t)w * NRM + v] = bs;
+      __syncthreads();
+    }
+    if (!grid_sync(ctrl, nwg, spin)) return;
+#pragma unroll
+    for (int v = 0; v < NRM; ++v) {
+      double s = 0.0;
+      for (int ww = 0; ww < nwg; ++ww) s += A.red[(size_t)ww * NRM + v];
+      tot[v] = s;
+    }
+  }
+  const double R1 = tot[2] > 0.0 ? tot[0] / tot[2] : tot[0];
+  const double R2 = tot[3] > 0.0 ? sqrt(tot[1] / tot[3]) : sqrt(tot[1]);
+  const double R = fmax(R1, R2);
+  int status = -100;   // continue
+  if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2]) || !isfinite(tot[3])) status = -6;
+  else if (R <= A.rtol) status = 0;
+  else if (A.iter >= A.max_iters) status = -3;
+  if (w == 0 && t == 0) {
+    if (A.hist) A.hist[A.iter] = R;
+    ctrl->r1 = R1;
+    ctrl->r2 = R2;
+    if (status != -100) {
+      ctrl->status = status;
+      ctrl->iters = A.iter;
+      ctrl->done = 1;
+    }
+  }
+  if (status != -100) return;
+
+  // --- assemble each set's diagonal block and factor it (one thread per set)
+  for (int s = s0 + t; s < s1; s += COARSE_NT) {
+    double B[Q * Q];
+    const double* g1 = A.g1 + (size_t)s * 36;
+    const double* kr = A.krow + (size_t)s * KROW;
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int l = 0; l < 6; ++l) B[m * Q + l] = g1[m * 6 + l];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int l = 0; l < 6; ++l) { B[(6 + q) * Q + l] = kr[q * 9 + l]; B[l * Q + 6 + q] = kr[q * 9 + l]; }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) B[(6 + q) * Q + 6 + p] = 0.5 * (kr[q * 9 + 6 + p] + kr[p * 9 + 6 + q]);
+    double* bd = A.bdiag + (size_t)s * Q * Q;
+#pragma unroll
+    for (int v = 0; v < Q * Q; ++v) bd[v] = B[v];
+    double sc[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) sc[k] = B[k * Q + k] > 0.0 ? 1.0 / sqrt(B[k * Q + k]) : 0.0;
+    double L[45];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      double dkk = sc[k] * sc[k] * B[k * Q + k];
+#pragma unroll
+      for (int j = 0; j < k; ++j) dkk -= L[lpk(k, j)] * L[lpk(k, j)];
+      const bool keep = sc[k] > 0.0 && dkk > 1e-9;
+      const double lkk = keep ? sqrt(dkk) : 0.0;
+      L[lpk(k, k)] = lkk;
+#pragma unroll
+      for (int i = k + 1; i < Q; ++i) {
+        double v = sc[i] * sc[k] * B[i * Q + k];
+#pragma unroll
+        for (int j = 0; j < k; ++j) v -= L[lpk(i, j)] * L[lpk(k, j)];
+        L[lpk(i, k)] = keep ? v / lkk : 0.0;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 45; ++v) A.lfac[(size_t)s * 45 + v] = L[v];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) A.bscale[(size_t)s * Q + k] = sc[k];
+  }
+  // --- PCG init: a = 0, r = P, z = B^+ r
+  for (int idx = t; idx < ns * Q; idx += COARSE_NT) {
+    const size_t e = (size_t)s0 * Q + idx;
+    A.a[e] = 0.0;
+    A.cr[e] = A.force[e];
+  }
+  __threadfence_block();
+  __syncthreads();
+  double rz_part = 0.0;
+  for (int s = s0 + t; s < s1; s += COARSE_NT) {
+    double rv[Q], zv[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) rv[k] = A.cr[(size_t)s * Q + k];
+    block_apply(A.lfac + (size_t)s * 45, A.bscale + (size_t)s * Q, rv, zv);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) { A.cz[(size_t)s * Q + k] = zv[k]; rz_part += rv[k] * zv[k]; }
+  }
+  int slot = 1;
+  double rz;
+  if (!grid_sum(rz_part, A.red, slot, ctrl, nwg, spin, sslot, rz)) return;
+  slot ^= 1;
+  const double rz0 = rz;
+  double beta = 0.0;
+  int it = 0;
+  double* pprev = A.cp0;
+  double* pcur = A.cp1;
+  for (; it < A.coarse_iters; ++it) {
+    if (!(rz > A.coarse_rtol * A.coarse_rtol * rz0) || !(rz > 0.0)) break;
+    // q = K_a p, p = z + beta p_prev computed on the fly for the neighbours
+    double pq_part = 0.0;
+    for (int idx = t; idx < ns * Q; idx += COARSE_NT) {
+      const int s = s0 + idx / Q, m = idx % Q;
+      const int I = s % g.mx, J = s / g.mx;
+      const double* bd = A.bdiag + (size_t)s * Q * Q + m * Q;
+      double q = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        const size_t e = (size_t)s * Q + l;
+        q += bd[l] * (beta != 0.0 ? A.cz[e] + beta * pprev[e] : A.cz[e]);
+      }
+      for (int dir = 0; dir < NDIR; ++dir) {
+        const int I2 = I + nb_di(dir), J2 = J + nb_dj(dir);
+        if (I2 < 0 || I2 >= g.mx || J2 < 0 || J2 >= g.my) continue;
+        const int s2 = J2 * g.mx + I2;
+        const double* ob = A.off + ((size_t)s * NDIR + dir) * Q * Q + m * Q;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) {
+          const size_t e = (size_t)s2 * Q + l;
+          q += ob[l] * (beta != 0.0 ? A.cz[e] + beta * pprev[e] : A.cz[e]);
+        }
+      }
+      const size_t e = (size_t)s * Q + m;
+      const double pv = beta != 0.0 ? A.cz[e] + beta * pprev[e] : A.cz[e];
+      pcur[e] = pv;
+      A.cq[e] = q;
+      pq_part += pv * q;
+    }
+    double pq;
+    if (!grid_sum(pq_part, A.red, slot, ctrl, nwg, spin, sslot, pq)) return;
+    slot ^= 1;
+    const double alpha = pq > 0.0 ? rz / pq : 0.0;
+    for (int idx = t; idx < ns * Q; idx += COARSE_NT) {
+      const size_t e = (size_t)s0 * Q + idx;
+      A.a[e] += alpha * pcur[e];
+      A.cr[e] -= alpha * A.cq[e];
+    }
+    __threadfence_block();
+    __syncthreads();
+    double rzn_part = 0.0;
+    for (int s = s0 + t; s < s1; s += COARSE_NT) {
+      double rv[Q], zv[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) rv[k] = A.cr[(size_t)s * Q + k];
+      block_apply(A.lfac + (size_t)s * 45, A.bscale + (size_t)s * Q, rv, zv);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) { A.cz[(size_t)s * Q + k] = zv[k]; rzn_part += rv[k] * zv[k]; }
+    }
+    double rzn;
+    if (!grid_sum(rzn_part, A.red, slot, ctrl, nwg, spin, sslot, rzn)) return;
+    slot ^= 1;
+    beta = rz > 0.0 ? rzn / rz : 0.0;
+    rz = rzn;
+    double* tmp = pprev; pprev = pcur; pcur = tmp;
+  }
+  if (w == 0 && t == 0) ctrl->coarse_iters += it;
+  // diagnostics: the upper-level system just solved
+  if (A.tr_kdiag)
+    for (size_t e = (size_t)s0 * Q * Q + t; e < (size_t)s1 * Q * Q; e += COARSE_NT) A.tr_kdiag[e] = A.bdiag[e];
+  if (A.tr_koff)
+    for (size_t e = (size_t)s0 * NDIR * Q * Q + t; e < (size_t)s1 * NDIR * Q * Q; e += COARSE_NT) A.tr_koff[e] = A.off[e];
+  if (A.tr_force)
+    for (size_t e = (size_t)s0 * Q + t; e < (size_t)s1 * Q; e += COARSE_NT) A.tr_force[e] = A.force[e];
+  if (A.tr_coef)
+    for (size_t e = (size_t)s0 * Q + t; e < (size_t)s1 * Q; e += COARSE_NT) A.tr_coef[e] = A.a[e];
+}
+
+// ---------------------------------------------------------------------------
+// Create time: constant 6x6 block of the translation/gradient modes,
+// G[m][l] = u_hat_m . k^Inner u_hat_l, m, l in 1..6 (Eq. 6 with Eq. 9-10).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_group1(Geo g, const float* __restrict__ ea,
+                                                const uint8_t* __restrict__ mask, double* g1) {
+  __shared__ double sacc[4][36];
+  const int s = blockIdx.x, I = s % g.mx, J = s / g.mx, E = g.E;
+  const int i0 = I * E, j0 = J * E, tw = min(E, g.nx - i0), th = min(E, g.ny - j0);
+  const size_t plane = (size_t)(g.ny + 2) * g.pitch;
+  const double inv_hs = 2.0 / E;
+  const int t = threadIdx.x;
+  double acc[36];
+#pragma unroll
+  for (int v = 0; v < 36; ++v) acc[v] = 0.0;
+  const int di[6] = {1, -1, 0, 0, -1, 1};
+  const int dj[6] = {0, 0, 1, -1, 1, -1};
+  const double nvx[6] = {1.0, 1.0, 0.5, 0.5, -0.5, -0.5};
+  const double nvy[6] = {0.0, 0.0, kS3, kS3, kS3, kS3};
+  for (int n = t; n < tw * th; n += 256) {
+    const int ai = i0 + n % tw, aj = j0 + n / tw;
+    const size_t pa = pidx(g, ai, aj);
+    if (mask[pa]) continue;
+    const float kr[6] = {ea[pa], ea[pa - 1], ea[plane + pa], ea[plane + pa - g.pitch],
+                         ea[2 * plane + pa], ea[2 * plane + pa - g.pitch + 1]};
+    double xa, ya;
+    set_coords(ai, aj, i0, j0, tw, th, inv_hs, xa, ya);
+    const double ux[6] = {1, 0, xa, ya, 0, 0}, uy[6] = {0, 1, 0, 0, xa, ya};
+    double wx[6] = {0, 0, 0, 0, 0, 0}, wy[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < 6; ++b) {
+      const int bi = ai + di[b], bj = aj + dj[b];
+      const bool in_set = bi >= i0 && bi < i0 + tw && bj >= j0 && bj < j0 + th &&
+                          mask[pidx(g, bi, bj)] == 0;
+      double xb, yb;
+      set_coords(bi, bj, i0, j0, tw, th, inv_hs, xb, yb);
+      const double vx[6] = {1, 0, xb, yb, 0, 0}, vy[6] = {0, 1, 0, 0, xb, yb};
+      for (int l = 0; l < 6; ++l) {
+        const double dx = ux[l] - (in_set ? vx[l] : 0.0), dy = uy[l] - (in_set ? vy[l] : 0.0);
+        const double sv = (double)kr[b] * (nvx[b] * dx + nvy[b] * dy);
+        wx[l] += sv * nvx[b];
+        wy[l] += sv * nvy[b];
+      }
+    }
+    for (int m = 0; m < 6; ++m)
+      for (int l = 0; l < 6; ++l) acc[m * 6 + l] += ux[m] * wx[l] + uy[m] * wy[l];
+  }
+#pragma unroll
+  for (int v = 0; v < 36; ++v) acc[v] = wave_sum(acc[v]);
+  if ((t & 63) == 0)
+    for (int v = 0; v < 36; ++v) sacc[t >> 6][v] = acc[v];
+  __syncthreads();
+  if (t < 36) {
+    const int m = t / 6, l = t % 6;
+    // symmetrise: the two triangles differ only by rounding
+    double s1 = 0.0, s2 = 0.0;
+    for (int w = 0; w < 4; ++w) { s1 += sacc[w][m * 6 + l]; s2 += sacc[w][l * 6 + m]; }
+    g1[(size_t)s * 36 + t] = 0.5 * (s1 + s2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up, copy and certification kernels.
+// ---------------------------------------------------------------------------
+__global__ void k_pad_copy(Geo g, const float* __restrict__ ea_user,
+                           const uint8_t* __restrict__ fixed_user, int ea_default,
+                           int fixed_default, float* ea, uint8_t* mask, int* stats) {
+  const size_t plane = (size_t)(g.ny + 2) * g.pitch;
+  const size_t nn = (size_t)g.nx * g.ny;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % g.nx), j = (int)(n / g.nx);
+    const size_t p = pidx(g, i, j);
+    const bool absent[3] = {i == g.nx - 1, j == g.ny - 1, i == 0 || j == g.ny - 1};
+    for (int d = 0; d < 3; ++d) {
+      float v = ea_default ? 1.0f : ea_user[(size_t)d * nn + n];
+      if (!absent[d] && !(v >= 0.0f && v <= 3.4e38f)) atomicAdd(&stats[0], 1);
+      ea[d * plane + p] = absent[d] ? 0.0f : v;
+    }
+    const uint8_t fx = fixed_default ? (uint8_t)(i == 0) : (uint8_t)(fixed_user[n] != 0);
+    mask[p] = fx;
+    if (fx) atomicAdd(&stats[1], 1);
+  }
+}
+
+template <typename T>
+__global__ void k_init_state(Geo g, const uint8_t* __restrict__ mask, const double2* u_fixed,
+                             const double2* u_user, int warm, double2* u0, double2* u1,
+                             void* d0v, void* d1v, double* a, Ctrl* ctrl) {
+  using T2 = typename V2<T>::type;
+  T2* d0 = reinterpret_cast<T2*>(d0v);
+  T2* d1 = reinterpret_cast<T2*>(d1v);
+  const size_t nn = (size_t)g.nx * g.ny;
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t nt = (size_t)gridDim.x * blockDim.x;
+  for (size_t n = tid; n < nn; n += nt) {
+    const int i = (int)(n % g.nx), j = (int)(n / g.nx);
+    const size_t p = pidx(g, i, j);
+    double2 u = make_double2(0.0, 0.0);
+    if (mask[p]) { if (u_fixed) u = u_fixed[n]; }
+    else if (warm) u = u_user[n];
+    u0[p] = u;
+    u1[p] = u;
+    d0[p] = mk2<T>((T)0, (T)0);
+    d1[p] = mk2<T>((T)0, (T)0);
+  }
+  for (size_t e = tid; e < (size_t)g.M * Q; e += nt) a[e] = 0.0;
+  if (tid == 0) {
+    ctrl->done = 0; ctrl->status = 0; ctrl->iters = 0; ctrl->err = 0;
+    ctrl->coarse_iters = 0; ctrl->r1 = 0.0; ctrl->r2 = 0.0;
+    ctrl->bar_count = 0u; ctrl->bar_gen = 0u;
+  }
+}
+
+__global__ void k_copy_out(Geo g, const double2* __restrict__ u_pad, double2* u_user) {
+  const size_t nn = (size_t)g.nx * g.ny;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    u_user[n] = u_pad[pidx(g, (int)(n % g.nx), (int)(n / g.nx))];
+  }
+}
+
+template <typename T>
+__global__ void k_copy_delta(Geo g, const void* d_pad, double2* out) {
+  using T2 = typename V2<T>::type;
+  const T2* d = reinterpret_cast<const T2*>(d_pad);
+  const size_t nn = (size_t)g.nx * g.ny;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const T2 v = d[pidx(g, (int)(n % g.nx), (int)(n / g.nx))];
+    out[n] = make_double2((double)v.x, (double)v.y);
+  }
+}
+
+// r = f - K u on unpadded arrays; per-block partials of sum|r|, sum r^2,
+// sum|f|, sum f^2 (free DOFs) and the energy 1/2 u.K.u - f.u (Eq. 2).
+constexpr int RES_NT = 256;
+constexpr int RES_NB_MAX = 4096;
+__global__ __launch_bounds__(RES_NT) void k_residual(Geo g, const float* __restrict__ ea,
+                                                     const uint8_t* __restrict__ mask,
+                                                     const double2* __restrict__ f,
+                                                     const double2* __restrict__ u, double2* r,
+                                                     double* partials) {
+  __shared__ double sl[RES_NT / 64][5];
+  const size_t plane = (size_t)(g.ny + 2) * g.pitch;
+  const size_t nn = (size_t)g.nx * g.ny;
+  double acc[5] = {0, 0, 0, 0, 0};
+  const int di[6] = {1, -1, 0, 0, -1, 1};
+  const int dj[6] = {0, 0, 1, -1, 1, -1};
+  const double nvx[6] = {1.0, 1.0, 0.5, 0.5, -0.5, -0.5};
+  const double nvy[6] = {0.0, 0.0, kS3, kS3, kS3, kS3};
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < nn;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % g.nx), j = (int)(n / g.nx);
+    const size_t p = pidx(g, i, j);
+    const float kr[6] = {ea[p], ea[p - 1], ea[plane + p], ea[plane + p - g.pitch],
+                         ea[2 * plane + p], ea[2 * plane + p - g.pitch + 1]};
+    const double2 ua = u[n];
+    double kx = 0.0, ky = 0.0, en = 0.0;
+    for (int b = 0; b < 6; ++b) {
+      const int bi = i + di[b], bj = j + dj[b];
+      if (bi < 0 || bi >= g.nx || bj < 0 || bj >= g.ny) continue;
+      const double2 ub = u[(size_t)bj * g.nx + bi];
+      const double e = nvx[b] * (ua.x - ub.x) + nvy[b] * (ua.y - ub.y);
+      const double s = (double)kr[b] * e;
+      kx += s * nvx[b];
+      ky += s * nvy[b];
+      en += 0.25 * s * e;        // each rod is seen from both ends
+    }
+    double2 rv = make_double2(0.0, 0.0);
+    if (!mask[p]) {
+      const double2 fv = f[n];
+      rv = make_double2(fv.x - kx, fv.y - ky);
+      acc[0] += fabs(rv.x) + fabs(rv.y);
+      acc[1] += rv.x * rv.x + rv.y * rv.y;
+      acc[2] += fabs(fv.x) + fabs(fv.y);
+      acc[3] += fv.x * fv.x + fv.y * fv.y;
+      en -= fv.x * ua.x + fv.y * ua.y;
+    }
+    acc[4] += en;
+    if (r) r[n] = rv;
+  }
+  for (int v = 0; v < 5; ++v) acc[v] = wave_sum(acc[v]);
+  if ((threadIdx.x & 63) == 0)
+    for (int v = 0; v < 5; ++v) sl[threadIdx.x >> 6][v] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double s = 0.0;
+    for (int w = 0; w < RES_NT / 64; ++w) s += sl[w][threadIdx.x];
+    partials[(size_t)blockIdx.x * 5 + threadIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(RES_NT) void k_reduce5(const double* partials, int nb, double* out) {
+  __shared__ double sl[RES_NT / 64][5];
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += RES_NT)
+    for (int v = 0; v < 5; ++v) acc[v] += partials[(size_t)b * 5 + v];
+  for (int v = 0; v < 5; ++v) acc[v] = wave_sum(acc[v]);
+  if ((threadIdx.x & 63) == 0)
+    for (int v = 0; v < 5; ++v) sl[threadIdx.x >> 6][v] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double s = 0.0;
+    for (int w = 0; w < RES_NT / 64; ++w) s += sl[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+namespace {
+int grid_for(size_t n, int nt, int cap) {
+  size_t b = (n + nt - 1) / nt;
+  if (b < 1) b = 1;
+  return (int)(b > (size_t)cap ? cap : b);
+}
+}  // namespace
+
+hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
+                       const TileArgs& a, hipStream_t stream) {
+  const dim3 grid(g.M);
+#define TL_TILE(T, E, NT) hipLaunchKernelGGL((k_tile<T, E, NT>), grid, dim3(NT), 0, stream, g, ea, mask, a)
+  if (mixed) {
+    if (g.E == 16) TL_TILE(float, 16, 256);
+    else if (g.E == 32) TL_TILE(float, 32, 256);
+    else if (g.E == 64) TL_TILE(float, 64, 1024);
+    else return hipErrorInvalidValue;
+  } else {
+    if (g.E == 16) TL_TILE(double, 16, 256);
+    else if (g.E == 32) TL_TILE(double, 32, 256);
+    else if (g.E == 64) TL_TILE(double, 64, 1024);
+    else return hipErrorInvalidValue;
+  }
+#undef TL_TILE
+  return hipGetLastError();
+}
+
+hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
+                          const OffArgs& a, hipStream_t stream) {
+  if (mixed) hipLaunchKernelGGL(k_offdiag<float>, dim3(g.M), dim3(256), 0, stream, g, ea, mask, a);
+  else hipLaunchKernelGGL(k_offdiag<double>, dim3(g.M), dim3(256), 0, stream, g, ea, mask, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream) {
+  hipLaunchKernelGGL(k_coarse, dim3(a.nwg), dim3(COARSE_NT), 0, stream, g, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_group1(const Geo& g, const float* ea, const uint8_t* mask, double* g1,
+                         hipStream_t stream) {
+  hipLaunchKernelGGL(k_group1, dim3(g.M), dim3(256), 0, stream, g, ea, mask, g1);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const Geo& g, const uint8_t* mask, const double2* u_fixed,
+                             const double2* u_user, int warm, double2* u0, double2* u1,
+                             void* d0, void* d1, bool mixed, double* a, Ctrl* ctrl,
+                             hipStream_t stream) {
+  const int nb = grid_for((size_t)g.nx * g.ny, 256, 8192);
+  if (mixed)
+    hipLaunchKernelGGL(k_init_state<float>, dim3(nb), dim3(256), 0, stream, g, mask, u_fixed,
+                       u_user, warm, u0, u1, d0, d1, a, ctrl);
+  else
+    hipLaunchKernelGGL(k_init_state<double>, dim3(nb), dim3(256), 0, stream, g, mask, u_fixed,
+                       u_user, warm, u0, u1, d0, d1, a, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_out(const Geo& g, const double2* u_pad, double2* u_user,
+                           hipStream_t stream) {
+  const int nb = grid_for((size_t)g.nx * g.ny, 256, 8192);
+  hipLaunchKernelGGL(k_copy_out, dim3(nb), dim3(256), 0, stream, g, u_pad, u_user);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_delta(bool mixed, const Geo& g, const void* d_pad, double2* out,
+                             hipStream_t stream) {
+  const int nb = grid_for((size_t)g.nx * g.ny, 256, 8192);
+  if (mixed) hipLaunchKernelGGL(k_copy_delta<float>, dim3(nb), dim3(256), 0, stream, g, d_pad, out);
+  else hipLaunchKernelGGL(k_copy_delta<double>, dim3(nb), dim3(256), 0, stream, g, d_pad, out);
+  return hipGetLastError();
+}
+
+size_t residual_partials(const Geo& g) {
+  return (size_t)grid_for((size_t)g.nx * g.ny, RES_NT, RES_NB_MAX) * 5;
+}
+
+hipError_t launch_residual(const Geo& g, const float* ea, const uint8_t* mask,
+                           const double2* f, const double2* u, double2* r, double* partials,
+                           double* out5, hipStream_t stream) {
+  const int nb = grid_for((size_t)g.nx * g.ny, RES_NT, RES_NB_MAX);
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RES_NT), 0, stream, g, ea, mask, f, u, r, partials);
+  hipLaunchKernelGGL(k_reduce5, dim3(1), dim3(RES_NT), 0, stream, partials, nb, out5);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_copy_stats(const Geo& g, const float* ea_user, const uint8_t* fixed_user,
+                                 int ea_default, int fixed_default, float* ea, uint8_t* mask,
+                                 int* stats, hipStream_t stream) {
+  const int nb = grid_for((size_t)g.nx * g.ny, 256, 8192);
+  hipLaunchKernelGGL(k_pad_copy, dim3(nb), dim3(256), 0, stream, g, ea_user, fixed_user,
+                     ea_default, fixed_default, ea, mask, stats);
+  return hipGetLastError();
+}
+
+}  // namespace tl

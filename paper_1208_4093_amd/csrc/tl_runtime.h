@@ -1,0 +1,80 @@
+// Host-side runtime structures shared by the single-solve, batch and server
+// paths.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "tl.h"
+#include "tl_internal.h"
+
+namespace tl {
+
+// Device state of one solve (allocated once per lattice and precision, or
+// per server request).
+struct Work {
+  Geo g{};
+  bool mixed = false;
+  int hist_cap = 0;
+  size_t bytes = 0;
+  double2* u[2] = {nullptr, nullptr};
+  void* d[2] = {nullptr, nullptr};
+  double *a = nullptr, *krow = nullptr, *force = nullptr, *nrm = nullptr, *off = nullptr;
+  double *bdiag = nullptr, *lfac = nullptr, *bscale = nullptr;
+  double *cr = nullptr, *cz = nullptr, *cp0 = nullptr, *cp1 = nullptr, *cq = nullptr;
+  double *red = nullptr, *hist = nullptr;
+  Ctrl* ctrl = nullptr;
+  Ctrl* ctrl_host = nullptr;       // pinned
+  std::vector<void*> allocs;
+
+  tl_status alloc(const Geo& g, bool mixed, int hist_cap);
+  void release();
+};
+
+struct Opts {
+  bool mixed;
+  double rtol;
+  int max_iters;
+  int inner;
+  int coarse_iters;
+  double coarse_rtol;
+  int warm;
+  tl_trace* trace;
+};
+
+}  // namespace tl
+
+struct tl_lattice {
+  tl::Geo g{};
+  int device = 0;
+  float* ea = nullptr;          // padded [3][ny + 2][pitch]
+  uint8_t* mask = nullptr;      // padded [ny + 2][pitch]
+  double2* ufix = nullptr;      // [ny][nx] prescribed displacements, or null (= 0)
+  double* g1 = nullptr;         // [M][36]
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  std::mutex mu;
+  tl::Work* work[2] = {nullptr, nullptr};
+  double* res_part = nullptr;   // certification scratch
+  double* res_out = nullptr;
+  double* out5_host = nullptr;  // pinned
+};
+
+namespace tl {
+
+int default_set_edge(int nx, int ny);
+Geo make_geo(int nx, int ny, int E);
+size_t padded_nodes(const Geo& g);
+size_t work_bytes(const Geo& g, bool mixed, int hist_cap);
+int coarse_workgroups(int M);
+void resolve_opts(const tl_opts* o, Opts* r);
+tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f, int k,
+                            hipStream_t st);
+tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, double* u,
+                    tl_info* info, hipStream_t st);
+tl_status certify(const tl_lattice* L, const double* f, const double* u, double* r,
+                  double out3[3], hipStream_t st);
+
+}  // namespace tl
