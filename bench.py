@@ -1,0 +1,233 @@
+"""Benchmark: DOF-solves/s of the hierarchical lattice solver on one MI355X.
+
+One step = one complete solve (to a relative residual of 1e-8 unless the
+workload says otherwise) of the workload's lattice, inputs already resident
+in HBM.  Prints one JSON line.
+
+Workloads (--workload):
+  c2 (default)  1024 x 1024 nodes (2,097,152 DOF), EA = 1, left edge clamped,
+                loads N(0, 1) (seed 0), sets of 32 x 32 nodes, float64 form
+                as the headline value, the mixed form measured beside it;
+  c1            64 x 64 nodes, sets of 16 x 16, relative residual 1e-10;
+  c3            16384 x 16384 nodes (536,870,912 DOF), EA lognormal(0, 0.5),
+                sets of 64 x 64, mixed form as the headline, residual 1e-10.
+
+The roofline object is computed from per-launch kernel durations measured
+with HIP events on the solve's stream inside the timed steps; the CPU
+baseline times the CPU oracle on the host for a bounded sample (see
+cpu_baseline()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF·solves/s to 1e-8 rel. residual, mixed vs FP64 form; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c1": dict(n=64, E=16, ea="unit", rtol=1e-10, headline="fp64",
+               desc="triangle lattice 64x64 nodes (8,192 DOF), EA=1, L=1, nodes i=0 clamped, "
+                    "loads N(0,1) seed 0, sets 16x16 nodes, stop at rel. residual 1e-10"),
+    "c2": dict(n=1024, E=32, ea="unit", rtol=1e-8, headline="fp64",
+               desc="triangle lattice 1024x1024 nodes (2,097,152 DOF), EA=1, L=1, left edge "
+                    "clamped, loads N(0,1) seed 0, sets 32x32 nodes, stop at rel. residual 1e-8"),
+    "c3": dict(n=16384, E=64, ea="lognormal", rtol=1e-10, headline="mixed",
+               desc="triangle lattice 16384x16384 nodes (536,870,912 DOF), EA lognormal(0,0.5), "
+                    "left edge clamped, loads N(0,1) seed 0, sets 64x64 nodes, mixed precision, "
+                    "stop at rel. residual 1e-10"),
+}
+
+# Algorithmic HBM bytes of one tile-kernel launch per lattice node: read u
+# (16) and write u (16), read f (16), read three rod stiffnesses (12), read
+# the clamp mask (1), read and write the relaxation increment (2 x 8 mixed,
+# 2 x 16 float64).  Halo re-reads are not counted.
+def tile_bytes_per_node(mixed: bool) -> int:
+    return 16 + 16 + 16 + 12 + 1 + (16 if mixed else 32)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(inst, rtol, budget_s=20.0):
+    """The CPU oracle (plain FP64 CSR assembly + block-Jacobi PCG, one thread)
+    on the same instance, bounded to about budget_s seconds.  When the PCG
+    has not reached rtol within the budget, the iterations still needed are
+    extrapolated from the log-linear decay of the residual over the second
+    half of the sample, and the solve time is assembly + (time per
+    iteration) x (iterations needed)."""
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    from oracle.solve import solve_pcg, system_of
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        S = system_of(inst)
+        t_asm = time.perf_counter() - t0
+        hist = []
+        t1 = time.perf_counter()
+        solve_pcg(S, rtol=rtol, max_seconds=max(1.0, budget_s - t_asm), history=hist)
+        t_pcg = time.perf_counter() - t1
+    n = len(hist)
+    its = np.array([h[0] for h in hist], dtype=float)
+    rel = np.array([h[1] for h in hist])
+    reached = np.flatnonzero(rel <= rtol)
+    if reached.size:
+        n_needed, how = float(its[reached[0]]), "converged within the sample"
+    else:
+        half = slice(n // 2, n)
+        slope = np.polyfit(its[half], np.log10(rel[half]), 1)[0]
+        n_needed = n + (math.log10(rtol) - math.log10(rel[-1])) / min(slope, -1e-12)
+        how = (f"extrapolated from {n} PCG iterations reaching {rel[-1]:.2e} "
+               f"(log-linear fit of the second half)")
+    t_solve = t_asm + t_pcg / max(n, 1) * n_needed
+    return {
+        "value": inst.dof / t_solve,
+        "unit": "DOF·solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle CSR assembly ({t_asm:.1f} s) + block-Jacobi PCG on the same "
+                   f"{inst.nx}x{inst.ny} instance, {t_pcg:.1f} s sampled, {how}; "
+                   f"{n_needed:.0f} iterations to {rtol:g}; one thread on "
+                   f"{platform.processor() or platform.machine()} ({os.cpu_count()} host cores)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the solver runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1208_4093_amd import tl
+    from workloads import make_instance
+
+    wl = WORKLOADS[args.workload]
+    n, E = wl["n"], wl["E"]
+    inst = make_instance(n, n, seed=0, ea=wl["ea"])
+    lat = tl.tl_lattice_create(n, n, ea=inst.ea, fixed=inst.fixed, set_edge=E)
+    f = torch.from_numpy(inst.f).to("cuda")
+    u = torch.zeros_like(f)
+    stream = torch.cuda.current_stream()
+
+    def run_form(precision):
+        mixed = precision == tl.TL_MIXED
+        for _ in range(args.warmup):
+            u.zero_()
+            tl.tl_solve(lat, f, u, stream=stream, precision=precision, rtol=wl["rtol"])
+        torch.cuda.synchronize()
+        lat_ms, infos = [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            u.zero_()
+            info = tl.tl_solve(lat, f, u, stream=stream, precision=precision, rtol=wl["rtol"],
+                               profile=True)
+            torch.cuda.synchronize()
+            lat_ms.append(1000.0 * (time.perf_counter() - ts))
+            infos.append(info)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        launches = sum(i["tile_launches"] for i in infos)
+        kern = {
+            "tile": sum(i["tile_ms"] for i in infos),
+            "offdiag": sum(i["offdiag_ms"] for i in infos),
+            "coarse": sum(i["coarse_ms"] for i in infos),
+        }
+        nodes = n * n
+        per_launch = {k: v / max(launches, 1) for k, v in kern.items()}
+        tile_gbs = tile_bytes_per_node(mixed) * nodes / (per_launch["tile"] * 1e-3) / 1e9
+        return {
+            "value": inst.dof * args.steps / wall,
+            "ms_per_step": 1000.0 * wall / args.steps,
+            "p50_ms": percentile(lat_ms, 50),
+            "p99_ms": percentile(lat_ms, 99),
+            "iters": infos[-1]["iters"],
+            "coarse_iters": infos[-1]["coarse_iters"],
+            "rel_res": max(infos[-1]["rel_res_l1"], infos[-1]["rel_res_l2"]),
+            "kernel_ms_per_launch": per_launch,
+            "kernel_share": {k: v / max(sum(kern.values()), 1e-30) for k, v in kern.items()},
+            "tile_gbs": tile_gbs,
+            "tile_bytes_per_launch": tile_bytes_per_node(mixed) * nodes,
+        }
+
+    fp64 = run_form(tl.TL_FP64)
+    mixed = run_form(tl.TL_MIXED)
+    head = fp64 if wl["headline"] == "fp64" else mixed
+    other = mixed if wl["headline"] == "fp64" else fp64
+    tile_ms = head["kernel_ms_per_launch"]["tile"]
+    roof = {
+        "kernel": "k_tile (update + float64 residual + LDS relaxation + set rows of the upper level)",
+        "bound": "hbm",
+        "achieved": head["tile_gbs"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": head["tile_gbs"] / HBM_PEAK_GBS,
+        "traffic": None,
+        "avg_launch_us": 1000.0 * tile_ms,
+        "algorithmic_bytes_per_launch": head["tile_bytes_per_launch"],
+        "time_share": head["kernel_share"]["tile"],
+    }
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "DOF·solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if wl["headline"] == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "dof": inst.dof, "set_edge": E,
+                   "form": wl["headline"]},
+        "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
+        "iters": head["iters"],
+        "coarse_iters": head["coarse_iters"],
+        "rel_res": head["rel_res"],
+        "kernel_ms_per_launch": head["kernel_ms_per_launch"],
+        ("mixed" if wl["headline"] == "fp64" else "fp64"): {
+            "value": other["value"], "ms_per_step": other["ms_per_step"],
+            "p50_ms": other["p50_ms"], "p99_ms": other["p99_ms"], "iters": other["iters"],
+            "rel_res": other["rel_res"], "kernel_ms_per_launch": other["kernel_ms_per_launch"],
+            "tile_gbs": other["tile_gbs"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline and n <= 4096:
+        out["cpu_baseline"] = cpu_baseline(inst, 1e-8 if wl["rtol"] >= 1e-8 else wl["rtol"],
+                                           args.cpu_budget)
+    elif not args.no_cpu_baseline:
+        out["cpu_baseline"] = None
+        out["cpu_baseline_note"] = ("not run: the oracle's CSR matrix of this lattice would not "
+                                    "fit host memory")
+    print(json.dumps(out), flush=True)
+    lat.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,8 @@ typedef struct {
     double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default    */
     int32_t warm_start;        /* 1: start from the free DOFs of u (else from 0)     */
     tl_trace* trace;           /* NULL, or diagnostics to fill                       */
+    int32_t profile;           /* 1: time every kernel launch with HIP events on the
+                                  solve's stream (fills the *_ms fields of tl_info)  */
 } tl_opts;
 
 typedef struct {
@@ -106,6 +108,11 @@ typedef struct {
     double energy;             /* total energy Pi of Eq. 2 at the returned u        */
     double ms;                 /* device time of the solve                         */
     int64_t coarse_iters;      /* upper-level PCG iterations summed over the solve  */
+    double tile_ms;            /* with opts->profile: summed duration of the tile
+                                  (update/residual/relaxation) kernel launches     */
+    double offdiag_ms;         /* ... of the boundary-block kernel launches         */
+    double coarse_ms;          /* ... of the upper-level kernel launches            */
+    int32_t tile_launches;     /* launches those sums cover (iterations that ran)   */
 } tl_info;
 
 /* Lattice geometry facts (for sizing buffers). */
@@ -140,8 +147,9 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
                          double* const* u_dev, const tl_opts* opts, tl_info* infos,
                          void* hip_stream);
 
-/* f <- f - K u (the residual of Eq. 7's bracket, float64) into r_dev (may be
- * NULL), and out[0..2] = R1, R2 (Eq. 19) and the energy Pi (Eq. 2) of u. */
+/* r = f - K u (float64; the bracket of Eq. 7) into r_dev (may be NULL), and
+ * out[0..2] = R1, R2 (Eq. 19, relative to the constrained right-hand side
+ * f - K_fc u_c) and the energy Pi (Eq. 2) of u. */
 tl_status tl_residual(tl_lattice* lat, const double* f_dev, const double* u_dev,
                       double* r_dev, double out[3], void* hip_stream);
 

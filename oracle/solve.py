@@ -60,9 +60,12 @@ def residual(sys_: System, u: np.ndarray) -> np.ndarray:
 
 
 def rel_residuals(sys_: System, u: np.ndarray):
-    """(R1, R2): ||f - K u|| / ||f|| over free DOFs in the 1- and 2-norm (Eq. 19)."""
+    """(R1, R2): ||f - K u|| / ||p|| over free DOFs in the 1- and 2-norm (Eq. 19).
+
+    p is the right-hand side of the constrained system, f_f - K_fc u_c; with
+    no prescribed displacement (the paper's setting) it is the load f."""
     r = residual(sys_, u)[sys_.free]
-    f = sys_.f[sys_.free]
+    f = sys_.rhs
     return (float(np.abs(r).sum() / np.abs(f).sum()),
             float(np.sqrt((r * r).sum()) / np.sqrt((f * f).sum())))
 

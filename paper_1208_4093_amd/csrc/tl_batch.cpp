@@ -44,6 +44,7 @@ struct Job {
   uint64_t ticket = 0;
   Clock::time_point t_submit, t_done;
   bool finished = false;
+  bool lock_lattice = true;  // false when the caller already holds the lattice lock
 };
 
 tl_status hip_status(hipError_t e) {
@@ -53,7 +54,7 @@ tl_status hip_status(hipError_t e) {
 tl_status start_job(Job* j, hipStream_t st) {
   hipError_t e = launch_init_state(j->L->g, j->L->mask, j->L->ufix, (const double2*)j->u,
                                    j->o.warm, j->w->u[0], j->w->u[1], j->w->d[0], j->w->d[1],
-                                   j->o.mixed, j->w->a, j->w->ctrl, st);
+                                   j->o.mixed, j->w->a, j->w->flags, j->w->ctrl, st);
   if (e != hipSuccess) return hip_status(e);
   j->k = 0;
   j->live = true;
@@ -72,8 +73,12 @@ void finish_job(Job* j, hipStream_t st) {
     double out3[3] = {0, 0, 0};
     tl_status cs = e == hipSuccess ? TL_OK : hip_status(e);
     if (cs == TL_OK) {
-      std::lock_guard<std::mutex> lock(j->L->mu);
-      cs = certify(j->L, j->f, j->u, nullptr, out3, st);
+      if (j->lock_lattice) {
+        std::lock_guard<std::mutex> lock(j->L->mu);
+        cs = certify(j->L, j->f, j->u, nullptr, out3, st);
+      } else {
+        cs = certify(j->L, j->f, j->u, nullptr, out3, st);
+      }
     }
     j->info.status = (tl_status)c.status;
     j->info.iters = kf;
@@ -233,6 +238,7 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
     j.f = f_dev[i];
     j.u = u_dev[i];
     j.o = o;
+    j.lock_lattice = false;
     tl_status s = TL_OK;
     if (seen[j.L] == 1) {
       Work*& w = j.L->work[o.mixed ? 1 : 0];

@@ -74,6 +74,8 @@ size_t work_bytes(const Geo& g, bool mixed, int hist_cap) {
 }
 
 void Work::release() {
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  events.clear();
   for (void* p : allocs) (void)hipFree(p);
   allocs.clear();
   if (ctrl_host) (void)hipHostFree(ctrl_host);
@@ -112,15 +114,19 @@ tl_status Work::alloc(const Geo& g_, bool mixed_, int hist_cap_) {
   TL_TRY(get(2 * COARSE_MAX_WG * NRM * sizeof(double), &p)); red = (double*)p;
   TL_TRY(get((size_t)hist_cap * sizeof(double), &p)); hist = (double*)p;
   TL_TRY(get(sizeof(Ctrl), &p)); ctrl = (Ctrl*)p;
+  TL_TRY(get(COARSE_MAX_WG * sizeof(unsigned), &p)); flags = (unsigned*)p;
   TL_TRY(hipHostMalloc((void**)&ctrl_host, sizeof(Ctrl), hipHostMallocDefault));
   bytes = work_bytes(g, mixed, hist_cap);
   return TL_OK;
 }
 
-int coarse_workgroups(int M) {
-  const int per = env_int("TL_COARSE_SETS_PER_WG", 16);
-  int n = (M + per - 1) / per;
-  return std::max(1, std::min(n, COARSE_MAX_WG));
+// Workgroups of the upper-level kernel: about `per` sets each, at most one
+// per CU, and few enough that each one's LDS window fits.
+int coarse_workgroups(const Geo& g) {
+  const int per = std::max(1, env_int("TL_COARSE_SETS_PER_WG", 16));
+  int n = std::max(1, std::min((g.M + per - 1) / per, COARSE_MAX_WG));
+  while (n < COARSE_MAX_WG && coarse_lds_bytes(g, n) > 150 * 1024) ++n;
+  return n;
 }
 
 void resolve_opts(const tl_opts* o, Opts* r) {
@@ -132,11 +138,13 @@ void resolve_opts(const tl_opts* o, Opts* r) {
   r->coarse_rtol = o && o->coarse_rtol > 0.0 ? o->coarse_rtol : 1e-4;
   r->warm = o ? o->warm_start : 0;
   r->trace = o ? o->trace : nullptr;
+  r->profile = o ? o->profile : 0;
 }
 
 // Enqueue outer iteration k of one solve.
 tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f, int k,
-                            hipStream_t st) {
+                            hipStream_t st, hipEvent_t* ev) {
+  if (ev) TL_TRY(hipEventRecord(ev[0], st));
   TileArgs ta;
   ta.u_in = w->u[k & 1];
   ta.u_out = w->u[(k + 1) & 1];
@@ -149,12 +157,15 @@ tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const d
   ta.nrm = w->nrm;
   ta.ctrl = w->ctrl;
   ta.inner_iters = o.inner;
+  ta.rhs_mode = L->ufix != nullptr;
   TL_TRY(launch_tile(o.mixed, L->g, L->ea, L->mask, ta, st));
+  if (ev) TL_TRY(hipEventRecord(ev[1], st));
   OffArgs oa;
   oa.d = w->d[(k + 1) & 1];
   oa.off = w->off;
   oa.ctrl = w->ctrl;
   TL_TRY(launch_offdiag(o.mixed, L->g, L->ea, L->mask, oa, st));
+  if (ev) TL_TRY(hipEventRecord(ev[2], st));
   CoarseArgs ca;
   ca.g1 = L->g1;
   ca.krow = w->krow;
@@ -171,6 +182,7 @@ tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const d
   ca.cp1 = w->cp1;
   ca.cq = w->cq;
   ca.red = w->red;
+  ca.flags = w->flags;
   ca.hist = (o.trace && o.trace->residual_history) ? o.trace->residual_history : w->hist;
   ca.tr_kdiag = o.trace ? o.trace->kdiag : nullptr;
   ca.tr_koff = o.trace ? o.trace->koff : nullptr;
@@ -182,16 +194,18 @@ tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const d
   ca.coarse_iters = o.coarse_iters;
   ca.coarse_rtol = o.coarse_rtol;
   ca.rtol = o.rtol;
-  ca.nwg = coarse_workgroups(L->g.M);
+  ca.nwg = coarse_workgroups(L->g);
+  ca.warm = env_int("TL_COARSE_WARM", 1);
   ca.spin_limit = 1u << 22;
   TL_TRY(launch_coarse(L->g, ca, st));
+  if (ev) TL_TRY(hipEventRecord(ev[3], st));
   return TL_OK;
 }
 
 tl_status certify(const tl_lattice* L, const double* f, const double* u, double* r,
                   double out3[3], hipStream_t st) {
-  TL_TRY(launch_residual(L->g, L->ea, L->mask, (const double2*)f, (const double2*)u, (double2*)r,
-                         L->res_part, L->res_out, st));
+  TL_TRY(launch_residual(L->g, L->ea, L->mask, (const double2*)f, (const double2*)u, L->ufix,
+                         (double2*)r, L->res_part, L->res_out, st));
   TL_TRY(hipMemcpyAsync(L->out5_host, L->res_out, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
   TL_TRY(hipStreamSynchronize(st));
   const double* o5 = L->out5_host;
@@ -207,18 +221,43 @@ tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, doub
   TL_TRY(hipEventCreate(&e0));
   TL_TRY(hipEventCreate(&e1));
   TL_TRY(launch_init_state(L->g, L->mask, L->ufix, (const double2*)u, o.warm, w->u[0], w->u[1],
-                           w->d[0], w->d[1], o.mixed, w->a, w->ctrl, st));
+                           w->d[0], w->d[1], o.mixed, w->a, w->flags, w->ctrl, st));
   TL_TRY(hipEventRecord(e0, st));
   int k = 0, chunk = 4;
   tl_status st_run = TL_OK;
+  double t_tile = 0.0, t_off = 0.0, t_coarse = 0.0;
+  int n_timed = 0;
   for (;;) {
+    const int k0 = k;
+    if (o.profile) {
+      while ((int)w->events.size() < 4 * chunk) {
+        hipEvent_t e;
+        TL_TRY(hipEventCreate(&e));
+        w->events.push_back(e);
+      }
+    }
     for (int c = 0; c < chunk && k <= o.max_iters; ++c, ++k) {
-      st_run = enqueue_iteration(L, w, o, f, k, st);
+      st_run = enqueue_iteration(L, w, o, f, k, st, o.profile ? &w->events[4 * c] : nullptr);
       if (st_run != TL_OK) break;
     }
     if (st_run != TL_OK) break;
     TL_TRY(hipMemcpyAsync(w->ctrl_host, w->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     TL_TRY(hipStreamSynchronize(st));
+    if (o.profile) {
+      // iterations after the one that stopped the solve are no-ops: not counted
+      const int last = w->ctrl_host->done ? w->ctrl_host->iters : k - 1;
+      for (int kk = k0; kk <= std::min(last, k - 1); ++kk) {
+        hipEvent_t* ev = &w->events[4 * (kk - k0)];
+        float a = 0.f, b = 0.f, c = 0.f;
+        TL_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));
+        TL_TRY(hipEventElapsedTime(&b, ev[1], ev[2]));
+        TL_TRY(hipEventElapsedTime(&c, ev[2], ev[3]));
+        t_tile += a;
+        t_off += b;
+        t_coarse += c;
+        ++n_timed;
+      }
+    }
     if (w->ctrl_host->err) { st_run = TL_E_DEVICE; break; }
     if (w->ctrl_host->done) break;
     if (k > o.max_iters) { st_run = TL_E_DEVICE; break; }
@@ -252,6 +291,10 @@ tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, doub
     info->energy = out3[2];
     info->ms = ms;
     info->coarse_iters = c.coarse_iters;
+    info->tile_ms = t_tile;
+    info->offdiag_ms = t_off;
+    info->coarse_ms = t_coarse;
+    info->tile_launches = n_timed;
   }
   if (c.status == 0 && !(std::isfinite(out3[0]) && std::isfinite(out3[1]))) return TL_E_NONFINITE;
   return (tl_status)c.status;

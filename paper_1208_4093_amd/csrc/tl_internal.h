@@ -46,7 +46,8 @@ struct Ctrl {
   int err;           // device-side abort (barrier time-out)
   long long coarse_iters;
   double r1, r2;     // relative residuals of the last checked iterate
-  unsigned bar_count, bar_gen;   // grid barrier of the upper-level kernel
+  unsigned bar_count;            // unused
+  unsigned bar_gen;              // generation of the last grid sum
 };
 
 template <typename T> struct V2;
@@ -65,6 +66,7 @@ struct TileArgs {
   double* nrm;           // [M][4]
   const Ctrl* ctrl;
   int inner_iters;
+  int rhs_mode;          // 1: prescribed displacements present, norms use f - K_fc u_c
 };
 
 struct CoarseArgs {
@@ -83,6 +85,7 @@ struct CoarseArgs {
   double* cp1;           // [9M] search direction, pong
   double* cq;            // [9M] K_a p
   double* red;           // [2][COARSE_MAX_WG][NRM] reduction slots
+  unsigned* flags;       // [COARSE_MAX_WG] arrival generations of the grid sums
   double* hist;          // [max_iters + 1] max(R1, R2) per outer iteration (may be null)
   double* tr_kdiag;      // optional copies of the solved system (diagnostics)
   double* tr_koff;
@@ -95,6 +98,7 @@ struct CoarseArgs {
   double coarse_rtol;
   double rtol;
   int nwg;
+  int warm;              // warm-start the upper-level PCG from the previous coefficients
   unsigned spin_limit;
 };
 
@@ -110,19 +114,21 @@ hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t*
 hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
                           const OffArgs& a, hipStream_t stream);
 hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream);
+size_t coarse_lds_bytes(const Geo& g, int nwg);
 hipError_t launch_group1(const Geo& g, const float* ea, const uint8_t* mask, double* g1,
                          hipStream_t stream);
 hipError_t launch_init_state(const Geo& g, const uint8_t* mask, const double2* u_fixed,
                              const double2* u_user, int warm, double2* u0,
                              double2* u1, void* d0, void* d1, bool mixed, double* a,
-                             Ctrl* ctrl, hipStream_t stream);
+                             unsigned* flags, Ctrl* ctrl, hipStream_t stream);
 hipError_t launch_copy_out(const Geo& g, const double2* u_pad, double2* u_user,
                            hipStream_t stream);
 hipError_t launch_copy_delta(bool mixed, const Geo& g, const void* d_pad, double2* out,
                              hipStream_t stream);
-// r = f - K u (unpadded f, u, r), and partial sums for R1, R2 and the energy.
+// r = f - K u (unpadded f, u, r), and sums for R1, R2 (relative to the
+// constrained right-hand side f - K_fc u_c, u_c = ufix or 0) and the energy.
 hipError_t launch_residual(const Geo& g, const float* ea, const uint8_t* mask,
-                           const double2* f, const double2* u, double2* r,
+                           const double2* f, const double2* u, const double2* ufix, double2* r,
                            double* partials, double* out5, hipStream_t stream);
 size_t residual_partials(const Geo& g);
 // Pad and copy the lattice description; stats[0] += non-finite or negative

@@ -18,6 +18,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace tl {
 
 namespace {
@@ -187,8 +189,25 @@ __global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea
     rod(kk[k][3], 1.0, 0.0, su[c - 1]);
     rod(kk[k][4], 0.5, kS3, su[c - W]);
     rod(kk[k][5], -0.5, kS3, su[c - W + 1]);
-    const double2 fv = A.f[(size_t)gj * g.nx + gi];
+    double2 fv = A.f[(size_t)gj * g.nx + gi];
     const double rx = fv.x - kx, ry = fv.y - ky;
+    if (A.rhs_mode) {
+      // right-hand side of the constrained system: f - K_fc u_c, i.e. the
+      // load plus the pull of every rod that ends on a clamped node
+      const int cb[6] = {c + 1, c - 1, c + W, c - W, c + W - 1, c - W + 1};
+      const long pb[6] = {1, -1, g.pitch, -(long)g.pitch, (long)g.pitch - 1, -(long)g.pitch + 1};
+      const double nbx[6] = {1.0, 1.0, 0.5, 0.5, -0.5, -0.5};
+      const double nby[6] = {0.0, 0.0, kS3, kS3, kS3, kS3};
+      const int kb[6] = {0, 3, 1, 4, 2, 5};
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        if (!mask[(long)p + pb[b]]) continue;
+        const double2 ub = su[cb[b]];
+        const double sv = (double)kk[k][kb[b]] * (nbx[b] * ub.x + nby[b] * ub.y);
+        fv.x += sv * nbx[b];
+        fv.y += sv * nby[b];
+      }
+    }
     r[k] = make_double2(rx, ry);
     double xi, eta;
     set_coords(gi, gj, i0, j0, tw, th, inv_hs, xi, eta);
@@ -453,55 +472,85 @@ __global__ __launch_bounds__(256) void k_offdiag(Geo g, const float* __restrict_
 
 // ---------------------------------------------------------------------------
 // Upper level: stop test of Eq. 19 and block-Jacobi PCG on Eq. 8.
+//
+// The grid is co-resident (at most one workgroup per CU).  Workgroup w owns
+// the sets [s0, s1) and keeps their PCG vectors in LDS.  Only two things
+// cross workgroups inside the kernel: the published z and p of each set
+// (read by the neighbouring sets' products) and the reduction partials.
+// Those are written and read with agent-scope relaxed atomics, which go to
+// the device-coherent level, and every wave waits for its stores to
+// complete before the barrier arrival; no L2-wide fence is needed.
 // ---------------------------------------------------------------------------
 namespace {
 
-// Grid-wide barrier over the co-resident workgroups of k_coarse.  Bounded:
-// a workgroup that waits longer than spin_limit polls flags an error, and
-// every later barrier then returns false at once, so the grid always drains.
-__device__ bool grid_sync(Ctrl* c, int nwg, unsigned spin_limit) {
-  __shared__ int ok;
-  __threadfence();
-  __syncthreads();
-  if (nwg == 1) return true;
-  if (threadIdx.x == 0) {
-    int good = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-    if (good) {
-      const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned arrived =
-          __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (arrived == (unsigned)nwg - 1u) {
-        __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        unsigned n = 0;
-        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-          if (++n > spin_limit ||
-              __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            __hip_atomic_store(&c->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            good = 0;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-    }
-    ok = good;
-  }
-  __syncthreads();
-  __threadfence();
-  return ok != 0;
+__device__ __forceinline__ void pub_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double pub_load(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sum over the grid; identical in every thread of every workgroup.
-__device__ bool grid_sum(double v, double* red, int slot, Ctrl* c, int nwg, unsigned spin,
-                         double* sslot, double& out) {
-  v = block_sum<COARSE_NT / 64>(v, sslot);
-  if (threadIdx.x == 0) red[(size_t)slot * COARSE_MAX_WG * NRM + blockIdx.x * NRM] = v;
-  if (!grid_sync(c, nwg, spin)) return false;
-  double s = 0.0;
-  for (int w = 0; w < nwg; ++w) s += red[(size_t)slot * COARSE_MAX_WG * NRM + w * NRM];
-  out = s;
+// Grid-wide sum of up to NRM values, which is also the grid barrier.
+// Workgroup w publishes its partials in slot `slot`, waits for its own
+// stores, then raises flags[w] to `gen`; every workgroup waits until all
+// flags have reached `gen` and adds the partials in workgroup order, so all
+// threads of all workgroups get the same bits.  No counter is shared, so
+// arrivals do not serialise on one address.  A workgroup can run at most one
+// sum ahead of the slowest, hence two slots and the wrap-safe ">= gen" test.
+// Bounded: after spin_limit polls the error flag is raised and every later
+// sum returns false at once, so the grid always drains.
+template <int NV>
+__device__ bool grid_sum(double (&v)[NV], double* red, unsigned* flags, unsigned gen, int slot,
+                         Ctrl* c, int nwg, unsigned spin, double* sslot) {
+  __shared__ int ok;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double bs = block_sum<COARSE_NT / 64>(v[k], sslot);
+    if (nwg == 1) v[k] = bs;
+    else if (threadIdx.x == 0) pub_store(&red[((size_t)slot * COARSE_MAX_WG + blockIdx.x) * NRM + k], bs);
+    __syncthreads();
+  }
+  if (nwg == 1) return true;
+  if (threadIdx.x < 64) {
+    int good = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    if (threadIdx.x == 0 && good) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_store(&flags[blockIdx.x], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned n = 0;
+    while (good) {
+      bool mine = true;
+      for (int w = threadIdx.x; w < nwg; w += 64)
+        mine &= (int)(__hip_atomic_load(&flags[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - gen) >= 0;
+      if (__all(mine)) break;
+      if (++n > spin || __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if (threadIdx.x == 0) __hip_atomic_store(&c->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (threadIdx.x == 0) ok = good;
+  }
+  __syncthreads();
+  if (!ok) return false;
+  // one wave adds the partials (lane l takes workgroups l, l + 64, ... in
+  // order, then a butterfly): the same tree in every workgroup
+  __shared__ double sv[NRM];
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = threadIdx.x; w < nwg; w += 64)
+        s += pub_load(&red[((size_t)slot * COARSE_MAX_WG + w) * NRM + k]);
+      s = wave_sum(s);
+      if (threadIdx.x == 0) sv[k] = s;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = sv[k];
+  __syncthreads();
   return true;
 }
 
@@ -531,9 +580,38 @@ __device__ void block_apply(const double* __restrict__ L, const double* __restri
   for (int k = 0; k < Q; ++k) z[k] *= sc[k];
 }
 
+// q = K_a p for the workgroup's own rows, p taken from the LDS window that
+// starts at set w0.
+__device__ __forceinline__ double coarse_row(const Geo& g, const CoarseArgs& A, int s, int m,
+                                             const double* lp, int w0) {
+  const int I = s % g.mx, J = s / g.mx;
+  const double* bd = A.bdiag + (size_t)s * Q * Q + m * Q;
+  const double* pv = lp + (size_t)(s - w0) * Q;
+  double q = 0.0;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) q += bd[l] * pv[l];
+#pragma unroll
+  for (int dir = 0; dir < NDIR; ++dir) {
+    const int I2 = I + nb_di(dir), J2 = J + nb_dj(dir);
+    if (I2 < 0 || I2 >= g.mx || J2 < 0 || J2 >= g.my) continue;
+    const double* ob = A.off + ((size_t)s * NDIR + dir) * Q * Q + m * Q;
+    const double* pn = lp + (size_t)(J2 * g.mx + I2 - w0) * Q;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) q += ob[l] * pn[l];
+  }
+  return q;
+}
+
 }  // namespace
 
+size_t coarse_lds_bytes(const Geo& g, int nwg) {
+  const int spw = (g.M + nwg - 1) / nwg;
+  const int win = std::min(g.M, spw + 2 * g.mx + 2);
+  return (size_t)(4 * spw + win) * Q * sizeof(double);
+}
+
 __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
+  extern __shared__ double lds[];
   __shared__ double sslot[COARSE_NT / 64];
   Ctrl* ctrl = A.ctrl;
   if (ctrl->done) return;
@@ -541,30 +619,29 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   const int M = g.M;
   const int spw = (M + nwg - 1) / nwg;
   const int s0 = min(M, w * spw), s1 = min(M, s0 + spw), ns = s1 - s0;
+  const int w0 = max(0, s0 - g.mx - 1), w1 = min(M, s1 + g.mx + 1);
+  const int win = ns > 0 ? w1 - w0 : 0;
   const unsigned spin = A.spin_limit;
+  const unsigned base = ctrl->bar_gen;    // generation of the last grid sum so far
+  unsigned nsync = 0;
+  double* lr = lds;                       // own r
+  double* lq = lr + (size_t)spw * Q;      // own K_a p
+  double* lx = lq + (size_t)spw * Q;      // own solution
+  double* lz = lx + (size_t)spw * Q;      // own z
+  double* lp = lz + (size_t)spw * Q;      // p over the window [w0, w1)
+  const int nrow = ns * Q;
 
   // --- global residual (Eq. 19, both norms) and stop test
-  double nv[NRM] = {0.0, 0.0, 0.0, 0.0};
+  double tot[NRM] = {0.0, 0.0, 0.0, 0.0};
   for (int s = s0 + t; s < s1; s += COARSE_NT) {
 #pragma unroll
-    for (int v = 0; v < NRM; ++v) nv[v] += A.nrm[(size_t)s * NRM + v];
+    for (int v = 0; v < NRM; ++v) tot[v] += A.nrm[(size_t)s * NRM + v];
   }
-  double tot[NRM];
-  {
-#pragma unroll
-    for (int v = 0; v < NRM; ++v) {
-      const double bs = block_sum<COARSE_NT / 64>(nv[v], sslot);
-      if (t == 0) A.red[(size_t)w * NRM + v] = bs;
-      __syncthreads();
-    }
-    if (!grid_sync(ctrl, nwg, spin)) return;
-#pragma unroll
-    for (int v = 0; v < NRM; ++v) {
-      double s = 0.0;
-      for (int ww = 0; ww < nwg; ++ww) s += A.red[(size_t)ww * NRM + v];
-      tot[v] = s;
-    }
-  }
+  // consecutive grid sums alternate between two slots, so a slot is only
+  // rewritten after the barrier that follows every read of it
+  int slot = 0;
+  if (!grid_sum<NRM>(tot, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
+  slot ^= 1;
   const double R1 = tot[2] > 0.0 ? tot[0] / tot[2] : tot[0];
   const double R2 = tot[3] > 0.0 ? sqrt(tot[1] / tot[3]) : sqrt(tot[1]);
   const double R = fmax(R1, R2);
@@ -580,6 +657,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
       ctrl->status = status;
       ctrl->iters = A.iter;
       ctrl->done = 1;
+      ctrl->bar_gen = base + nsync;
     }
   }
   if (status != -100) return;
@@ -629,27 +707,50 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
 #pragma unroll
     for (int k = 0; k < Q; ++k) A.bscale[(size_t)s * Q + k] = sc[k];
   }
-  // --- PCG init: a = 0, r = P, z = B^+ r
-  for (int idx = t; idx < ns * Q; idx += COARSE_NT) {
-    const size_t e = (size_t)s0 * Q + idx;
-    A.a[e] = 0.0;
-    A.cr[e] = A.force[e];
-  }
-  __threadfence_block();
   __syncthreads();
-  double rz_part = 0.0;
-  for (int s = s0 + t; s < s1; s += COARSE_NT) {
-    double rv[Q], zv[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) rv[k] = A.cr[(size_t)s * Q + k];
-    block_apply(A.lfac + (size_t)s * 45, A.bscale + (size_t)s * Q, rv, zv);
-#pragma unroll
-    for (int k = 0; k < Q; ++k) { A.cz[(size_t)s * Q + k] = zv[k]; rz_part += rv[k] * zv[k]; }
+
+  // --- start: a = 0, or (warm start) the previous coefficients scaled by
+  //     the step that minimises the upper-level energy along them, which
+  //     keeps the energy decrease of the outer iteration.
+  const bool warm = A.warm && A.iter > 0;
+  for (int e = t; e < nrow; e += COARSE_NT) {
+    lr[e] = A.force[(size_t)s0 * Q + e];
+    lx[e] = warm ? A.a[(size_t)s0 * Q + e] : 0.0;
   }
-  int slot = 1;
-  double rz;
-  if (!grid_sum(rz_part, A.red, slot, ctrl, nwg, spin, sslot, rz)) return;
+  if (warm) {
+    for (int e = t; e < win * Q; e += COARSE_NT) lp[e] = A.a[(size_t)w0 * Q + e];
+    __syncthreads();
+    double nd[2] = {0.0, 0.0};
+    for (int e = t; e < nrow; e += COARSE_NT) {
+      const double q = coarse_row(g, A, s0 + e / Q, e % Q, lp, w0);
+      lq[e] = q;
+      nd[0] += lx[e] * lr[e];
+      nd[1] += lx[e] * q;
+    }
+    if (!grid_sum<2>(nd, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
+    slot ^= 1;
+    const double th = (nd[1] > 0.0 && nd[0] > 0.0) ? nd[0] / nd[1] : 0.0;
+    for (int e = t; e < nrow; e += COARSE_NT) {
+      lx[e] *= th;
+      lr[e] -= th * lq[e];
+    }
+  }
+  __syncthreads();
+  double rz_v[1] = {0.0};
+  for (int s = s0 + t; s < s1; s += COARSE_NT) {
+    double zv[Q];
+    const int o = (s - s0) * Q;
+    block_apply(A.lfac + (size_t)s * 45, A.bscale + (size_t)s * Q, lr + o, zv);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      lz[o + k] = zv[k];
+      pub_store(&A.cz[(size_t)s * Q + k], zv[k]);
+      rz_v[0] += lr[o + k] * zv[k];
+    }
+  }
+  if (!grid_sum<1>(rz_v, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
   slot ^= 1;
+  double rz = rz_v[0];
   const double rz0 = rz;
   double beta = 0.0;
   int it = 0;
@@ -657,63 +758,52 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   double* pcur = A.cp1;
   for (; it < A.coarse_iters; ++it) {
     if (!(rz > A.coarse_rtol * A.coarse_rtol * rz0) || !(rz > 0.0)) break;
-    // q = K_a p, p = z + beta p_prev computed on the fly for the neighbours
-    double pq_part = 0.0;
-    for (int idx = t; idx < ns * Q; idx += COARSE_NT) {
-      const int s = s0 + idx / Q, m = idx % Q;
-      const int I = s % g.mx, J = s / g.mx;
-      const double* bd = A.bdiag + (size_t)s * Q * Q + m * Q;
-      double q = 0.0;
-#pragma unroll
-      for (int l = 0; l < Q; ++l) {
-        const size_t e = (size_t)s * Q + l;
-        q += bd[l] * (beta != 0.0 ? A.cz[e] + beta * pprev[e] : A.cz[e]);
-      }
-      for (int dir = 0; dir < NDIR; ++dir) {
-        const int I2 = I + nb_di(dir), J2 = J + nb_dj(dir);
-        if (I2 < 0 || I2 >= g.mx || J2 < 0 || J2 >= g.my) continue;
-        const int s2 = J2 * g.mx + I2;
-        const double* ob = A.off + ((size_t)s * NDIR + dir) * Q * Q + m * Q;
-#pragma unroll
-        for (int l = 0; l < Q; ++l) {
-          const size_t e = (size_t)s2 * Q + l;
-          q += ob[l] * (beta != 0.0 ? A.cz[e] + beta * pprev[e] : A.cz[e]);
-        }
-      }
-      const size_t e = (size_t)s * Q + m;
-      const double pv = beta != 0.0 ? A.cz[e] + beta * pprev[e] : A.cz[e];
-      pcur[e] = pv;
-      A.cq[e] = q;
-      pq_part += pv * q;
+    // p = z + beta p_prev over the window; own entries are published
+    for (int e = t; e < win * Q; e += COARSE_NT) {
+      const size_t ge = (size_t)w0 * Q + e;
+      const double pv = beta != 0.0 ? pub_load(&A.cz[ge]) + beta * pub_load(&pprev[ge])
+                                     : pub_load(&A.cz[ge]);
+      lp[e] = pv;
+      if (ge >= (size_t)s0 * Q && ge < (size_t)s1 * Q) pub_store(&pcur[ge], pv);
     }
-    double pq;
-    if (!grid_sum(pq_part, A.red, slot, ctrl, nwg, spin, sslot, pq)) return;
-    slot ^= 1;
-    const double alpha = pq > 0.0 ? rz / pq : 0.0;
-    for (int idx = t; idx < ns * Q; idx += COARSE_NT) {
-      const size_t e = (size_t)s0 * Q + idx;
-      A.a[e] += alpha * pcur[e];
-      A.cr[e] -= alpha * A.cq[e];
-    }
-    __threadfence_block();
     __syncthreads();
-    double rzn_part = 0.0;
-    for (int s = s0 + t; s < s1; s += COARSE_NT) {
-      double rv[Q], zv[Q];
-#pragma unroll
-      for (int k = 0; k < Q; ++k) rv[k] = A.cr[(size_t)s * Q + k];
-      block_apply(A.lfac + (size_t)s * 45, A.bscale + (size_t)s * Q, rv, zv);
-#pragma unroll
-      for (int k = 0; k < Q; ++k) { A.cz[(size_t)s * Q + k] = zv[k]; rzn_part += rv[k] * zv[k]; }
+    double pq_v[1] = {0.0};
+    for (int e = t; e < nrow; e += COARSE_NT) {
+      const double q = coarse_row(g, A, s0 + e / Q, e % Q, lp, w0);
+      lq[e] = q;
+      pq_v[0] += lp[(size_t)(s0 - w0) * Q + e] * q;
     }
-    double rzn;
-    if (!grid_sum(rzn_part, A.red, slot, ctrl, nwg, spin, sslot, rzn)) return;
+    if (!grid_sum<1>(pq_v, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
     slot ^= 1;
-    beta = rz > 0.0 ? rzn / rz : 0.0;
-    rz = rzn;
+    const double alpha = pq_v[0] > 0.0 ? rz / pq_v[0] : 0.0;
+    for (int e = t; e < nrow; e += COARSE_NT) {
+      lx[e] += alpha * lp[(size_t)(s0 - w0) * Q + e];
+      lr[e] -= alpha * lq[e];
+    }
+    __syncthreads();
+    double rzn_v[1] = {0.0};
+    for (int s = s0 + t; s < s1; s += COARSE_NT) {
+      double zv[Q];
+      const int o = (s - s0) * Q;
+      block_apply(A.lfac + (size_t)s * 45, A.bscale + (size_t)s * Q, lr + o, zv);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        lz[o + k] = zv[k];
+        pub_store(&A.cz[(size_t)s * Q + k], zv[k]);
+        rzn_v[0] += lr[o + k] * zv[k];
+      }
+    }
+    if (!grid_sum<1>(rzn_v, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
+    slot ^= 1;
+    beta = rz > 0.0 ? rzn_v[0] / rz : 0.0;
+    rz = rzn_v[0];
     double* tmp = pprev; pprev = pcur; pcur = tmp;
   }
-  if (w == 0 && t == 0) ctrl->coarse_iters += it;
+  for (int e = t; e < nrow; e += COARSE_NT) A.a[(size_t)s0 * Q + e] = lx[e];
+  if (w == 0 && t == 0) {
+    ctrl->coarse_iters += it;
+    ctrl->bar_gen = base + nsync;
+  }
   // diagnostics: the upper-level system just solved
   if (A.tr_kdiag)
     for (size_t e = (size_t)s0 * Q * Q + t; e < (size_t)s1 * Q * Q; e += COARSE_NT) A.tr_kdiag[e] = A.bdiag[e];
@@ -722,7 +812,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   if (A.tr_force)
     for (size_t e = (size_t)s0 * Q + t; e < (size_t)s1 * Q; e += COARSE_NT) A.tr_force[e] = A.force[e];
   if (A.tr_coef)
-    for (size_t e = (size_t)s0 * Q + t; e < (size_t)s1 * Q; e += COARSE_NT) A.tr_coef[e] = A.a[e];
+    for (int e = t; e < nrow; e += COARSE_NT) A.tr_coef[(size_t)s0 * Q + e] = lx[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -812,7 +902,7 @@ __global__ void k_pad_copy(Geo g, const float* __restrict__ ea_user,
 template <typename T>
 __global__ void k_init_state(Geo g, const uint8_t* __restrict__ mask, const double2* u_fixed,
                              const double2* u_user, int warm, double2* u0, double2* u1,
-                             void* d0v, void* d1v, double* a, Ctrl* ctrl) {
+                             void* d0v, void* d1v, double* a, unsigned* flags, Ctrl* ctrl) {
   using T2 = typename V2<T>::type;
   T2* d0 = reinterpret_cast<T2*>(d0v);
   T2* d1 = reinterpret_cast<T2*>(d1v);
@@ -831,6 +921,7 @@ __global__ void k_init_state(Geo g, const uint8_t* __restrict__ mask, const doub
     d1[p] = mk2<T>((T)0, (T)0);
   }
   for (size_t e = tid; e < (size_t)g.M * Q; e += nt) a[e] = 0.0;
+  for (size_t e = tid; e < (size_t)COARSE_MAX_WG; e += nt) flags[e] = 0u;
   if (tid == 0) {
     ctrl->done = 0; ctrl->status = 0; ctrl->iters = 0; ctrl->err = 0;
     ctrl->coarse_iters = 0; ctrl->r1 = 0.0; ctrl->r2 = 0.0;
@@ -865,7 +956,8 @@ constexpr int RES_NB_MAX = 4096;
 __global__ __launch_bounds__(RES_NT) void k_residual(Geo g, const float* __restrict__ ea,
                                                      const uint8_t* __restrict__ mask,
                                                      const double2* __restrict__ f,
-                                                     const double2* __restrict__ u, double2* r,
+                                                     const double2* __restrict__ u,
+                                                     const double2* __restrict__ ufix, double2* r,
                                                      double* partials) {
   __shared__ double sl[RES_NT / 64][5];
   const size_t plane = (size_t)(g.ny + 2) * g.pitch;
@@ -897,10 +989,23 @@ __global__ __launch_bounds__(RES_NT) void k_residual(Geo g, const float* __restr
     if (!mask[p]) {
       const double2 fv = f[n];
       rv = make_double2(fv.x - kx, fv.y - ky);
+      double2 rhs = fv;
+      if (ufix) {
+        // f - K_fc u_c: rods ending on clamped nodes pull with k n (n . u_c)
+        for (int b = 0; b < 6; ++b) {
+          const int bi = i + di[b], bj = j + dj[b];
+          if (bi < 0 || bi >= g.nx || bj < 0 || bj >= g.ny) continue;
+          if (!mask[pidx(g, bi, bj)]) continue;
+          const double2 ub = ufix[(size_t)bj * g.nx + bi];
+          const double sv = (double)kr[b] * (nvx[b] * ub.x + nvy[b] * ub.y);
+          rhs.x += sv * nvx[b];
+          rhs.y += sv * nvy[b];
+        }
+      }
       acc[0] += fabs(rv.x) + fabs(rv.y);
       acc[1] += rv.x * rv.x + rv.y * rv.y;
-      acc[2] += fabs(fv.x) + fabs(fv.y);
-      acc[3] += fv.x * fv.x + fv.y * fv.y;
+      acc[2] += fabs(rhs.x) + fabs(rhs.y);
+      acc[3] += rhs.x * rhs.x + rhs.y * rhs.y;
       en -= fv.x * ua.x + fv.y * ua.y;
     }
     acc[4] += en;
@@ -971,7 +1076,16 @@ hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8
 }
 
 hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream) {
-  hipLaunchKernelGGL(k_coarse, dim3(a.nwg), dim3(COARSE_NT), 0, stream, g, a);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_coarse,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const size_t lds = coarse_lds_bytes(g, a.nwg);
+  if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_coarse, dim3(a.nwg), dim3(COARSE_NT), lds, stream, g, a);
   return hipGetLastError();
 }
 
@@ -983,15 +1097,15 @@ hipError_t launch_group1(const Geo& g, const float* ea, const uint8_t* mask, dou
 
 hipError_t launch_init_state(const Geo& g, const uint8_t* mask, const double2* u_fixed,
                              const double2* u_user, int warm, double2* u0, double2* u1,
-                             void* d0, void* d1, bool mixed, double* a, Ctrl* ctrl,
-                             hipStream_t stream) {
+                             void* d0, void* d1, bool mixed, double* a, unsigned* flags,
+                             Ctrl* ctrl, hipStream_t stream) {
   const int nb = grid_for((size_t)g.nx * g.ny, 256, 8192);
   if (mixed)
     hipLaunchKernelGGL(k_init_state<float>, dim3(nb), dim3(256), 0, stream, g, mask, u_fixed,
-                       u_user, warm, u0, u1, d0, d1, a, ctrl);
+                       u_user, warm, u0, u1, d0, d1, a, flags, ctrl);
   else
     hipLaunchKernelGGL(k_init_state<double>, dim3(nb), dim3(256), 0, stream, g, mask, u_fixed,
-                       u_user, warm, u0, u1, d0, d1, a, ctrl);
+                       u_user, warm, u0, u1, d0, d1, a, flags, ctrl);
   return hipGetLastError();
 }
 
@@ -1015,10 +1129,10 @@ size_t residual_partials(const Geo& g) {
 }
 
 hipError_t launch_residual(const Geo& g, const float* ea, const uint8_t* mask,
-                           const double2* f, const double2* u, double2* r, double* partials,
-                           double* out5, hipStream_t stream) {
+                           const double2* f, const double2* u, const double2* ufix, double2* r,
+                           double* partials, double* out5, hipStream_t stream) {
   const int nb = grid_for((size_t)g.nx * g.ny, RES_NT, RES_NB_MAX);
-  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RES_NT), 0, stream, g, ea, mask, f, u, r, partials);
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RES_NT), 0, stream, g, ea, mask, f, u, ufix, r, partials);
   hipLaunchKernelGGL(k_reduce5, dim3(1), dim3(RES_NT), 0, stream, partials, nb, out5);
   return hipGetLastError();
 }

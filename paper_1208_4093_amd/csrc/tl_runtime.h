@@ -26,8 +26,10 @@ struct Work {
   double *cr = nullptr, *cz = nullptr, *cp0 = nullptr, *cp1 = nullptr, *cq = nullptr;
   double *red = nullptr, *hist = nullptr;
   Ctrl* ctrl = nullptr;
+  unsigned* flags = nullptr;       // grid-sum arrival flags of the upper-level kernel
   Ctrl* ctrl_host = nullptr;       // pinned
   std::vector<void*> allocs;
+  std::vector<hipEvent_t> events;  // kernel timing (opts.profile), 4 per iteration of a chunk
 
   tl_status alloc(const Geo& g, bool mixed, int hist_cap);
   void release();
@@ -42,6 +44,7 @@ struct Opts {
   double coarse_rtol;
   int warm;
   tl_trace* trace;
+  int profile;
 };
 
 }  // namespace tl
@@ -68,10 +71,10 @@ int default_set_edge(int nx, int ny);
 Geo make_geo(int nx, int ny, int E);
 size_t padded_nodes(const Geo& g);
 size_t work_bytes(const Geo& g, bool mixed, int hist_cap);
-int coarse_workgroups(int M);
+int coarse_workgroups(const Geo& g);
 void resolve_opts(const tl_opts* o, Opts* r);
 tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f, int k,
-                            hipStream_t st);
+                            hipStream_t st, hipEvent_t* ev = nullptr);
 tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, double* u,
                     tl_info* info, hipStream_t st);
 tl_status certify(const tl_lattice* L, const double* f, const double* u, double* r,

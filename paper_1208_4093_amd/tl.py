@@ -42,13 +42,14 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int32),
                 ("inner_iters", C.c_int32), ("coarse_iters", C.c_int32),
                 ("coarse_rtol", C.c_double), ("warm_start", C.c_int32),
-                ("trace", C.POINTER(Trace))]
+                ("trace", C.POINTER(Trace)), ("profile", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int32), ("rel_res_l1", C.c_double),
                 ("rel_res_l2", C.c_double), ("energy", C.c_double), ("ms", C.c_double),
-                ("coarse_iters", C.c_int64)]
+                ("coarse_iters", C.c_int64), ("tile_ms", C.c_double), ("offdiag_ms", C.c_double),
+                ("coarse_ms", C.c_double), ("tile_launches", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -205,7 +206,7 @@ def tl_lattice_create(nx, ny, ea=None, fixed=None, u_fixed=None, set_edge=0, str
 
 
 def make_opts(precision=TL_FP64, rtol=1e-8, max_iters=0, inner_iters=0, coarse_iters=0,
-              coarse_rtol=0.0, warm_start=False, trace=None):
+              coarse_rtol=0.0, warm_start=False, trace=None, profile=False):
     o = Opts()
     o.precision = int(precision)
     o.rtol = float(rtol)
@@ -215,6 +216,7 @@ def make_opts(precision=TL_FP64, rtol=1e-8, max_iters=0, inner_iters=0, coarse_i
     o.coarse_rtol = float(coarse_rtol)
     o.warm_start = 1 if warm_start else 0
     o.trace = C.pointer(trace) if trace is not None else C.POINTER(Trace)()
+    o.profile = 1 if profile else 0
     return o
 
 

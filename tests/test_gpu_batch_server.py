@@ -1,0 +1,103 @@
+"""Batched solves and the continuous-batching server, through the C ABI:
+every lattice's result is the same alone and in a batch or a served mix
+(bit for bit: each lattice's kernels, set edge and reduction orders depend
+only on that lattice), and matches the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle.solve import rel_residuals, solve, system_of
+from workloads import make_instance
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+tl = pytest.importorskip("paper_1208_4093_amd.tl")
+
+SHAPES = [(40, 33, 16, "lognormal", 1), (64, 64, 16, "unit", 2), (130, 70, 32, "lognormal", 3),
+          (33, 95, 16, "lognormal", 4), (90, 90, 64, "unit", 5)]
+
+
+def _setup():
+    lats, fs, insts = [], [], []
+    for nx, ny, E, ea, seed in SHAPES:
+        inst = make_instance(nx, ny, seed=seed, ea=ea)
+        insts.append(inst)
+        lats.append(tl.tl_lattice_create(nx, ny, ea=inst.ea, fixed=inst.fixed, set_edge=E))
+        fs.append(torch.from_numpy(inst.f).cuda())
+    return insts, lats, fs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_alone_and_oracle(precision):
+    insts, lats, fs = _setup()
+    alone = []
+    for lat, f in zip(lats, fs):
+        u = torch.zeros_like(f)
+        tl.tl_solve(lat, f, u, precision=precision, rtol=1e-10)
+        alone.append(u.cpu().numpy())
+    us = [torch.zeros_like(f) for f in fs]
+    st, infos = tl.tl_solve_batch(lats, fs, us, precision=precision, rtol=1e-10)
+    assert st == tl.TL_OK
+    for inst, u, ua, info in zip(insts, us, alone, infos):
+        ub = u.cpu().numpy()
+        assert np.array_equal(ub, ua)
+        S = system_of(inst)
+        ref = solve(S)
+        assert np.linalg.norm(ub.reshape(-1) - ref) <= 1e-8 * np.linalg.norm(ref)
+        assert max(info["rel_res_l1"], info["rel_res_l2"]) <= 1e-10
+
+
+def test_batch_with_repeated_lattice():
+    insts, lats, fs = _setup()
+    f2 = torch.from_numpy(make_instance(40, 33, seed=99, ea="lognormal").f).cuda()
+    L = [lats[0], lats[0], lats[1]]
+    F = [fs[0], f2, fs[1]]
+    us = [torch.zeros_like(f) for f in F]
+    st, infos = tl.tl_solve_batch(L, F, us, precision=1, rtol=1e-9)
+    assert st == tl.TL_OK
+    for lat, f, u in zip(L, F, us):
+        ua = torch.zeros_like(f)
+        tl.tl_solve(lat, f, ua, precision=1, rtol=1e-9)
+        assert torch.equal(u, ua)
+
+
+def test_server_results_equal_alone_under_overlap():
+    insts, lats, fs = _setup()
+    alone = []
+    for lat, f in zip(lats, fs):
+        u = torch.zeros_like(f)
+        tl.tl_solve(lat, f, u, precision=1, rtol=1e-9)
+        alone.append(u.cpu().numpy())
+    srv = tl.tl_server_create(1 << 32, 3)
+    us = [torch.zeros_like(f) for f in fs]
+    tickets = []
+    for k, (lat, f, u) in enumerate(zip(lats, fs, us)):
+        tickets.append(tl.tl_submit(srv, lat, f, u, precision=1, rtol=1e-9))
+        time.sleep(0.002 * k)          # staggered arrivals join running rounds
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets) and time.time() - t0 < 60:
+        for tk in tickets:
+            if tk in done:
+                continue
+            st, info = tl.tl_poll(srv, tk)
+            if st != tl.TL_PENDING:
+                done[tk] = (st, info)
+        time.sleep(0.001)
+    srv.close()
+    assert len(done) == len(tickets)
+    for tk, u, ua in zip(tickets, us, alone):
+        st, info = done[tk]
+        assert st == tl.TL_OK and info["ms"] > 0.0
+        assert np.array_equal(u.cpu().numpy(), ua)
+
+
+def test_server_budget_limits():
+    insts, lats, fs = _setup()
+    srv = tl.tl_server_create(1 << 16, 2)          # 64 KiB: the 130 x 70 lattice never fits
+    u = torch.zeros_like(fs[2])
+    with pytest.raises(tl.TLError) as ei:
+        tl.tl_submit(srv, lats[2], fs[2], u, precision=1, rtol=1e-9)
+    assert ei.value.status == tl.TL_E_BUDGET
+    srv.close()

@@ -175,12 +175,13 @@ def test_affine_patch_on_gpu():
     inst.fixed[:, [0, -1]] = 1
     inst.u_fixed[:] = np.where(inst.fixed[..., None].astype(bool), field, 0.0)
     inst.f[:] = 0.0
-    inst.f[1, 1, 0] = 1e-3       # a tiny load so that ||f|| > 0; superpose its oracle response
     S = system_of(inst)
     us = solve(S)
-    u, info, _ = gpu_solve(inst, 16, 0, 1e-11)
-    assert info["status"] == tl.TL_OK
-    assert np.abs(u.reshape(-1) - us).max() <= 1e-8 * np.abs(us).max()
+    assert np.abs(us.reshape(ny, nx, 2) - field).max() <= 1e-12 * np.abs(field).max()
+    for precision in (0, 1):
+        u, info, _ = gpu_solve(inst, 16, precision, 1e-11)
+        assert info["status"] == tl.TL_OK
+        assert np.abs(u - field).max() <= 1e-8 * np.abs(field).max()
 
 
 def test_nonfinite_load_is_reported():
