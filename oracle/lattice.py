@@ -80,9 +80,9 @@ def assemble(nx: int, ny: int, ea: np.ndarray) -> sp.csr_matrix:
     r, c, v = r[order], c[order], v[order]
     key = r * ndof + c
     start = np.flatnonzero(np.r_[True, key[1:] != key[:-1]])
-    K = sp.csr_matrix((np.add.reduceat(v, start), (r[start], c[start])), shape=(ndof, ndof))
-    K.sort_indices()
-    return K
+    rows_u, cols_u = r[start], c[start]              # sorted by (row, col), unique
+    indptr = np.r_[0, np.cumsum(np.bincount(rows_u, minlength=ndof))]
+    return sp.csr_matrix((np.add.reduceat(v, start), cols_u, indptr), shape=(ndof, ndof))
 
 
 def free_mask(fixed: np.ndarray) -> np.ndarray:
