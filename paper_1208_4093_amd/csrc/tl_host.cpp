@@ -67,8 +67,9 @@ size_t padded_nodes(const Geo& g) { return (size_t)(g.ny + 2) * g.pitch; }
 size_t work_bytes(const Geo& g, bool mixed, int hist_cap) {
   const size_t np = padded_nodes(g), M = g.M;
   size_t b = 2 * np * sizeof(double2) + 2 * np * (mixed ? sizeof(float2) : sizeof(double2));
-  b += M * (Q + KROW + Q + NRM + NDIR * Q * Q + Q * Q + 45 + Q + 5 * Q) * sizeof(double);
-  b += 2 * COARSE_MAX_WG * NRM * sizeof(double) + (size_t)hist_cap * sizeof(double);
+  b += M * (Q + KROW + Q + NRM + NDIR * Q * Q + 2 * Q * Q + 10 * Q) * sizeof(double);
+  b += 2 * COARSE_MAX_WG * REDW * sizeof(double) + (size_t)hist_cap * sizeof(double);
+  b += COARSE_MAX_WG * sizeof(unsigned);
   b += sizeof(Ctrl);
   return b;
 }
@@ -104,14 +105,13 @@ tl_status Work::alloc(const Geo& g_, bool mixed_, int hist_cap_) {
   TL_TRY(get(M * NRM * sizeof(double), &p)); nrm = (double*)p;
   TL_TRY(get(M * NDIR * Q * Q * sizeof(double), &p)); off = (double*)p;
   TL_TRY(get(M * Q * Q * sizeof(double), &p)); bdiag = (double*)p;
-  TL_TRY(get(M * 45 * sizeof(double), &p)); lfac = (double*)p;
-  TL_TRY(get(M * Q * sizeof(double), &p)); bscale = (double*)p;
-  TL_TRY(get(M * Q * sizeof(double), &p)); cr = (double*)p;
-  TL_TRY(get(M * Q * sizeof(double), &p)); cz = (double*)p;
-  TL_TRY(get(M * Q * sizeof(double), &p)); cp0 = (double*)p;
-  TL_TRY(get(M * Q * sizeof(double), &p)); cp1 = (double*)p;
-  TL_TRY(get(M * Q * sizeof(double), &p)); cq = (double*)p;
-  TL_TRY(get(2 * COARSE_MAX_WG * NRM * sizeof(double), &p)); red = (double*)p;
+  TL_TRY(get(M * Q * Q * sizeof(double), &p)); binv = (double*)p;
+  double** vecs[] = {&cr, &cu, &cw, &cz, &cq, &cs, &cp, &cn, &pub0, &pub1};
+  for (double** v : vecs) {
+    TL_TRY(get(M * Q * sizeof(double), &p));
+    *v = (double*)p;
+  }
+  TL_TRY(get(2 * COARSE_MAX_WG * REDW * sizeof(double), &p)); red = (double*)p;
   TL_TRY(get((size_t)hist_cap * sizeof(double), &p)); hist = (double*)p;
   TL_TRY(get(sizeof(Ctrl), &p)); ctrl = (Ctrl*)p;
   TL_TRY(get(COARSE_MAX_WG * sizeof(unsigned), &p)); flags = (unsigned*)p;
@@ -120,13 +120,20 @@ tl_status Work::alloc(const Geo& g_, bool mixed_, int hist_cap_) {
   return TL_OK;
 }
 
-// Workgroups of the upper-level kernel: about `per` sets each, at most one
-// per CU, and few enough that each one's LDS window fits.
-int coarse_workgroups(const Geo& g) {
-  const int per = std::max(1, env_int("TL_COARSE_SETS_PER_WG", 16));
-  int n = std::max(1, std::min((g.M + per - 1) / per, COARSE_MAX_WG));
-  while (n < COARSE_MAX_WG && coarse_lds_bytes(g, n) > 150 * 1024) ++n;
-  return n;
+// Launch shape of the upper-level kernel: about `per` sets per workgroup, at
+// most one workgroup per CU and few enough that each one's LDS windows fit;
+// the own vectors and blocks go to LDS when there is room.
+constexpr size_t kCoarseLdsCap = 150 * 1024;
+
+CoarseShape coarse_shape(const Geo& g) {
+  const int per = std::max(1, env_int("TL_COARSE_SETS_PER_WG", 8));
+  CoarseShape c;
+  c.nwg = std::max(1, std::min((g.M + per - 1) / per, COARSE_MAX_WG));
+  while (c.nwg < COARSE_MAX_WG && coarse_lds_bytes(g, c.nwg, 0, 0) > kCoarseLdsCap) ++c.nwg;
+  c.vec_lds = coarse_lds_bytes(g, c.nwg, 1, 0) <= kCoarseLdsCap;
+  c.blk_lds = c.vec_lds && coarse_lds_bytes(g, c.nwg, 1, 1) <= kCoarseLdsCap;
+  if (env_int("TL_COARSE_NO_LDS", 0)) c.vec_lds = c.blk_lds = 0;
+  return c;
 }
 
 void resolve_opts(const tl_opts* o, Opts* r) {
@@ -163,6 +170,10 @@ tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const d
   OffArgs oa;
   oa.d = w->d[(k + 1) & 1];
   oa.off = w->off;
+  oa.g1 = L->g1;
+  oa.krow = w->krow;
+  oa.bdiag = w->bdiag;
+  oa.binv = w->binv;
   oa.ctrl = w->ctrl;
   TL_TRY(launch_offdiag(o.mixed, L->g, L->ea, L->mask, oa, st));
   if (ev) TL_TRY(hipEventRecord(ev[2], st));
@@ -173,14 +184,18 @@ tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const d
   ca.nrm = w->nrm;
   ca.off = w->off;
   ca.bdiag = w->bdiag;
-  ca.lfac = w->lfac;
-  ca.bscale = w->bscale;
+  ca.binv = w->binv;
   ca.a = w->a;
   ca.cr = w->cr;
+  ca.cu = w->cu;
+  ca.cw = w->cw;
   ca.cz = w->cz;
-  ca.cp0 = w->cp0;
-  ca.cp1 = w->cp1;
   ca.cq = w->cq;
+  ca.cs = w->cs;
+  ca.cp = w->cp;
+  ca.cn = w->cn;
+  ca.pub0 = w->pub0;
+  ca.pub1 = w->pub1;
   ca.red = w->red;
   ca.flags = w->flags;
   ca.hist = (o.trace && o.trace->residual_history) ? o.trace->residual_history : w->hist;
@@ -194,7 +209,10 @@ tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const d
   ca.coarse_iters = o.coarse_iters;
   ca.coarse_rtol = o.coarse_rtol;
   ca.rtol = o.rtol;
-  ca.nwg = coarse_workgroups(L->g);
+  const CoarseShape cs = coarse_shape(L->g);
+  ca.nwg = cs.nwg;
+  ca.vec_lds = cs.vec_lds;
+  ca.blk_lds = cs.blk_lds;
   ca.warm = env_int("TL_COARSE_WARM", 1);
   ca.spin_limit = 1u << 22;
   TL_TRY(launch_coarse(L->g, ca, st));

@@ -29,6 +29,7 @@ constexpr int NRM = 4;          // sum|r|, sum r^2, sum|f|, sum f^2 (free DOFs)
 constexpr int TILE_OUT = KROW + Q + NRM;
 constexpr int COARSE_NT = 256;  // threads per upper-level workgroup
 constexpr int COARSE_MAX_WG = 256;
+constexpr int REDW = 8;         // values per workgroup and slot of a grid sum
 
 // Set-grid neighbour offsets (dI, dJ); direction d and d + 3 are opposite.
 __host__ __device__ constexpr int nb_di(int d) { return d == 0 ? 1 : d == 2 ? -1 : d == 3 ? -1 : d == 5 ? 1 : 0; }
@@ -75,16 +76,20 @@ struct CoarseArgs {
   const double* force;   // [M][9]
   const double* nrm;     // [M][4]
   const double* off;     // [M][6][81]
-  double* bdiag;         // [M][81]
-  double* lfac;          // [M][45]
-  double* bscale;        // [M][9]
-  double* a;             // [M][9] solution (coefficients)
-  double* cr;            // [9M] residual
-  double* cz;            // [9M] preconditioned residual
-  double* cp0;           // [9M] search direction, ping
-  double* cp1;           // [9M] search direction, pong
-  double* cq;            // [9M] K_a p
-  double* red;           // [2][COARSE_MAX_WG][NRM] reduction slots
+  double* bdiag;         // [M][81] assembled diagonal blocks
+  double* binv;          // [M][81] their pseudo-inverses (block-Jacobi preconditioner)
+  double* a;             // [9M] solution (coefficients); also the warm start
+  double* cr;            // [9M] pipelined-PCG vectors, own rows only
+  double* cu;
+  double* cw;
+  double* cz;
+  double* cq;
+  double* cs;
+  double* cp;
+  double* cn;
+  double* pub0;          // [9M] published vectors read by neighbouring sets (ping)
+  double* pub1;          // [9M] (pong)
+  double* red;           // [2][COARSE_MAX_WG][REDW] reduction slots
   unsigned* flags;       // [COARSE_MAX_WG] arrival generations of the grid sums
   double* hist;          // [max_iters + 1] max(R1, R2) per outer iteration (may be null)
   double* tr_kdiag;      // optional copies of the solved system (diagnostics)
@@ -99,12 +104,18 @@ struct CoarseArgs {
   double rtol;
   int nwg;
   int warm;              // warm-start the upper-level PCG from the previous coefficients
+  int vec_lds;           // 1: own PCG vectors in LDS
+  int blk_lds;           // 1: own blocks staged in LDS
   unsigned spin_limit;
 };
 
 struct OffArgs {
   const void* d;         // T2 padded relaxation increments of this iteration
   double* off;           // [M][6][81]
+  const double* g1;      // [M][36]
+  const double* krow;    // [M][27]
+  double* bdiag;         // [M][81] assembled diagonal blocks
+  double* binv;          // [M][81] their pseudo-inverses
   const Ctrl* ctrl;
 };
 
@@ -114,7 +125,7 @@ hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t*
 hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
                           const OffArgs& a, hipStream_t stream);
 hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream);
-size_t coarse_lds_bytes(const Geo& g, int nwg);
+size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds);
 hipError_t launch_group1(const Geo& g, const float* ea, const uint8_t* mask, double* g1,
                          hipStream_t stream);
 hipError_t launch_init_state(const Geo& g, const uint8_t* mask, const double2* u_fixed,

@@ -402,6 +402,64 @@ __global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea
   }
 }
 
+namespace {
+
+__device__ __forceinline__ int lpk(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Block-Jacobi preconditioner of one set: the symmetric pseudo-inverse of its
+// 9x9 diagonal block, B^+ = S L^-T L^-1 S, from a Jacobi-scaled Cholesky
+// factorisation S B S = L L^T that drops (zeroes) a mode whose pivot falls
+// below 1e-9, i.e. a mode that is, to that level, a combination of the
+// modes before it.
+__device__ void block_pinv(const double* B, double* Binv) {
+  double sc[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) sc[k] = B[k * Q + k] > 0.0 ? 1.0 / sqrt(B[k * Q + k]) : 0.0;
+  double L[45];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double dkk = sc[k] * sc[k] * B[k * Q + k];
+#pragma unroll
+    for (int j = 0; j < k; ++j) dkk -= L[lpk(k, j)] * L[lpk(k, j)];
+    const bool keep = sc[k] > 0.0 && dkk > 1e-9;
+    const double lkk = keep ? sqrt(dkk) : 0.0;
+    L[lpk(k, k)] = lkk;
+#pragma unroll
+    for (int i = k + 1; i < Q; ++i) {
+      double v = sc[i] * sc[k] * B[i * Q + k];
+#pragma unroll
+      for (int j = 0; j < k; ++j) v -= L[lpk(i, j)] * L[lpk(k, j)];
+      L[lpk(i, k)] = keep ? v / lkk : 0.0;
+    }
+  }
+  // X = L^-1 (lower triangular; rows and columns of dropped modes stay 0)
+  double X[45];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+#pragma unroll
+    for (int i = j; i < Q; ++i) {
+      const double lii = L[lpk(i, i)];
+      double v = i == j ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = j; k < i; ++k) v -= L[lpk(i, k)] * X[lpk(k, j)];
+      X[lpk(i, j)] = lii > 0.0 ? v / lii : 0.0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = i; k < Q; ++k) v += X[lpk(k, i)] * X[lpk(k, j)];
+      v *= sc[i] * sc[j];
+      Binv[i * Q + j] = v;
+      Binv[j * Q + i] = v;
+    }
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // Upper-level blocks between neighbouring sets, from the rods their common
 // boundary cuts: K[Im][Jl] = -sum_rods k (n . u_hat_m^I(a)) (n . u_hat_l^J(c)).
@@ -468,6 +526,25 @@ __global__ __launch_bounds__(256) void k_offdiag(Geo g, const float* __restrict_
     }
     __syncthreads();
   }
+  // the set's diagonal block (constant translation/gradient part + the rows
+  // of the relaxation modes from the tile kernel) and its pseudo-inverse
+  if (t == 0) {
+    double B[Q * Q];
+    const double* g1 = A.g1 + (size_t)s * 36;
+    const double* kr = A.krow + (size_t)s * KROW;
+    for (int m = 0; m < 6; ++m)
+      for (int l = 0; l < 6; ++l) B[m * Q + l] = g1[m * 6 + l];
+    for (int q = 0; q < 3; ++q)
+      for (int l = 0; l < 6; ++l) { B[(6 + q) * Q + l] = kr[q * 9 + l]; B[l * Q + 6 + q] = kr[q * 9 + l]; }
+    for (int q = 0; q < 3; ++q)
+      for (int p = 0; p < 3; ++p) B[(6 + q) * Q + 6 + p] = 0.5 * (kr[q * 9 + 6 + p] + kr[p * 9 + 6 + q]);
+    double* bd = A.bdiag + (size_t)s * Q * Q;
+    for (int v = 0; v < Q * Q; ++v) bd[v] = B[v];
+    double Bi[Q * Q];
+    block_pinv(B, Bi);
+    double* bi = A.binv + (size_t)s * Q * Q;
+    for (int v = 0; v < Q * Q; ++v) bi[v] = Bi[v];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -490,7 +567,7 @@ __device__ __forceinline__ double pub_load(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide sum of up to NRM values, which is also the grid barrier.
+// Grid-wide sum of up to REDW values, which is also the grid barrier.
 // Workgroup w publishes its partials in slot `slot`, waits for its own
 // stores, then raises flags[w] to `gen`; every workgroup waits until all
 // flags have reached `gen` and adds the partials in workgroup order, so all
@@ -499,15 +576,29 @@ __device__ __forceinline__ double pub_load(const double* p) {
 // sum ahead of the slowest, hence two slots and the wrap-safe ">= gen" test.
 // Bounded: after spin_limit polls the error flag is raised and every later
 // sum returns false at once, so the grid always drains.
+// Publish this workgroup's partials of a grid sum (slot `slot`) and wait
+// until every workgroup has published (its flag reached `gen`).  Workgroup w
+// writes its partials, waits for its own stores, then raises flags[w]; no
+// counter is shared, so arrivals do not serialise on one address.  A
+// workgroup can run at most one sum ahead of the slowest, hence two slots and
+// the wrap-safe ">= gen" test.  Bounded: after spin_limit polls the error
+// flag is raised and every later call returns false at once, so the grid
+// always drains.  With one workgroup the partials are left in sv and no
+// memory round trip is made.
 template <int NV>
-__device__ bool grid_sum(double (&v)[NV], double* red, unsigned* flags, unsigned gen, int slot,
-                         Ctrl* c, int nwg, unsigned spin, double* sslot) {
+__device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* flags,
+                                  unsigned gen, int slot, Ctrl* c, int nwg, unsigned spin,
+                                  double* sslot, double* sv) {
   __shared__ int ok;
+  static_assert(NV <= REDW, "too many values for one grid sum");
+  __builtin_amdgcn_s_waitcnt(0);   // every wave's published stores have completed
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const double bs = block_sum<COARSE_NT / 64>(v[k], sslot);
-    if (nwg == 1) v[k] = bs;
-    else if (threadIdx.x == 0) pub_store(&red[((size_t)slot * COARSE_MAX_WG + blockIdx.x) * NRM + k], bs);
+    if (threadIdx.x == 0) {
+      if (nwg == 1) sv[k] = bs;
+      else pub_store(&red[((size_t)slot * COARSE_MAX_WG + blockIdx.x) * REDW + k], bs);
+    }
     __syncthreads();
   }
   if (nwg == 1) return true;
@@ -533,86 +624,82 @@ __device__ bool grid_sum(double (&v)[NV], double* red, unsigned* flags, unsigned
     if (threadIdx.x == 0) ok = good;
   }
   __syncthreads();
-  if (!ok) return false;
-  // one wave adds the partials (lane l takes workgroups l, l + 64, ... in
-  // order, then a butterfly): the same tree in every workgroup
-  __shared__ double sv[NRM];
-  if (threadIdx.x < 64) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      for (int w = threadIdx.x; w < nwg; w += 64)
-        s += pub_load(&red[((size_t)slot * COARSE_MAX_WG + w) * NRM + k]);
-      s = wave_sum(s);
-      if (threadIdx.x == 0) sv[k] = s;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = sv[k];
-  __syncthreads();
-  return true;
+  return ok != 0;
 }
 
-__device__ __forceinline__ int lpk(int i, int j) { return i * (i + 1) / 2 + j; }
-
-// z = B^+ r for one set: scaled factor with dropped (dependent) modes zero.
-__device__ void block_apply(const double* __restrict__ L, const double* __restrict__ sc,
-                            const double* r, double* z) {
-  double y[Q];
+// Add the published partials (after grid_publish_wait) into sv: one wave,
+// lane l takes workgroups l, l + 64, ... in order, then a butterfly; the same
+// tree in every workgroup, so every workgroup gets the same bits.  Only
+// thread 0 writes sv; the caller synchronises before reading it.
+template <int NV>
+__device__ void grid_collect(const double* red, int slot, int nwg, double* sv) {
+  if (nwg == 1 || threadIdx.x >= 64) return;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    double v = sc[k] * r[k];
-#pragma unroll
-    for (int j = 0; j < k; ++j) v -= L[lpk(k, j)] * y[j];
-    const double dkk = L[lpk(k, k)];
-    y[k] = dkk > 0.0 ? v / dkk : 0.0;
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = threadIdx.x; w < nwg; w += 64)
+      s += pub_load(&red[((size_t)slot * COARSE_MAX_WG + w) * REDW + k]);
+    s = wave_sum(s);
+    if (threadIdx.x == 0) sv[k] = s;
   }
-#pragma unroll
-  for (int k = Q - 1; k >= 0; --k) {
-    double v = y[k];
-#pragma unroll
-    for (int i = k + 1; i < Q; ++i) v -= L[lpk(i, k)] * z[i];
-    const double dkk = L[lpk(k, k)];
-    z[k] = dkk > 0.0 ? v / dkk : 0.0;
-  }
-#pragma unroll
-  for (int k = 0; k < Q; ++k) z[k] *= sc[k];
 }
 
-// q = K_a p for the workgroup's own rows, p taken from the LDS window that
-// starts at set w0.
-__device__ __forceinline__ double coarse_row(const Geo& g, const CoarseArgs& A, int s, int m,
-                                             const double* lp, int w0) {
+// (K_a v) for one row of the workgroup's own sets, v from the LDS window that
+// starts at set w0.  bd / ob point at the own sets' diagonal and neighbour
+// blocks (an LDS copy or global memory), indexed from set s0.
+__device__ __forceinline__ double coarse_row(const Geo& g, const double* bd, const double* ob,
+                                             int s, int s0, int m, const double* lv, int w0) {
   const int I = s % g.mx, J = s / g.mx;
-  const double* bd = A.bdiag + (size_t)s * Q * Q + m * Q;
-  const double* pv = lp + (size_t)(s - w0) * Q;
+  const double* b = bd + (size_t)(s - s0) * Q * Q + m * Q;
+  const double* pv = lv + (size_t)(s - w0) * Q;
   double q = 0.0;
 #pragma unroll
-  for (int l = 0; l < Q; ++l) q += bd[l] * pv[l];
+  for (int l = 0; l < Q; ++l) q += b[l] * pv[l];
 #pragma unroll
   for (int dir = 0; dir < NDIR; ++dir) {
     const int I2 = I + nb_di(dir), J2 = J + nb_dj(dir);
     if (I2 < 0 || I2 >= g.mx || J2 < 0 || J2 >= g.my) continue;
-    const double* ob = A.off + ((size_t)s * NDIR + dir) * Q * Q + m * Q;
-    const double* pn = lp + (size_t)(J2 * g.mx + I2 - w0) * Q;
+    const double* o = ob + ((size_t)(s - s0) * NDIR + dir) * Q * Q + m * Q;
+    const double* pn = lv + (size_t)(J2 * g.mx + I2 - w0) * Q;
 #pragma unroll
-    for (int l = 0; l < Q; ++l) q += ob[l] * pn[l];
+    for (int l = 0; l < Q; ++l) q += o[l] * pn[l];
   }
   return q;
 }
 
-}  // namespace
-
-size_t coarse_lds_bytes(const Geo& g, int nwg) {
-  const int spw = (g.M + nwg - 1) / nwg;
-  const int win = std::min(g.M, spw + 2 * g.mx + 2);
-  return (size_t)(4 * spw + win) * Q * sizeof(double);
+// One row of B^+ v for the own set s, v (own rows) in LDS at lv (set s0 first).
+__device__ __forceinline__ double pinv_row(const double* bi, int s, int s0, int m,
+                                           const double* lv) {
+  const double* b = bi + (size_t)(s - s0) * Q * Q + m * Q;
+  const double* v = lv + (size_t)(s - s0) * Q;
+  double z = 0.0;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) z += b[l] * v[l];
+  return z;
 }
 
+}  // namespace
+
+// Dynamic LDS of the upper-level kernel: two windows of the set vectors and
+// the own rows of the vector being preconditioned, plus (when they fit) the
+// own sets' PCG vectors and their blocks.
+size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds) {
+  const size_t spw = (size_t)(g.M + nwg - 1) / nwg;
+  const size_t win = std::min((size_t)g.M, spw + 2 * (size_t)g.mx + 2);
+  size_t b = (spw + 2 * win) * Q * sizeof(double);
+  if (vec_lds) b += 8 * spw * Q * sizeof(double);
+  if (blk_lds) b += spw * (NDIR + 2) * Q * Q * sizeof(double);
+  return b;
+}
+
+// Upper-level kernel.  Pipelined block-Jacobi PCG (the Ghysels-Vanroose
+// recurrences): per iteration one grid sum carries both dot products and
+// orders the publication of m = B^+ w, whose neighbour values the product
+// n = K_a m needs, so one grid synchronisation per iteration.
 __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   extern __shared__ double lds[];
   __shared__ double sslot[COARSE_NT / 64];
+  __shared__ double sv[REDW];
   Ctrl* ctrl = A.ctrl;
   if (ctrl->done) return;
   const int w = blockIdx.x, nwg = gridDim.x, t = threadIdx.x;
@@ -621,185 +708,279 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   const int s0 = min(M, w * spw), s1 = min(M, s0 + spw), ns = s1 - s0;
   const int w0 = max(0, s0 - g.mx - 1), w1 = min(M, s1 + g.mx + 1);
   const int win = ns > 0 ? w1 - w0 : 0;
-  const unsigned spin = A.spin_limit;
-  const unsigned base = ctrl->bar_gen;    // generation of the last grid sum so far
-  unsigned nsync = 0;
-  double* lr = lds;                       // own r
-  double* lq = lr + (size_t)spw * Q;      // own K_a p
-  double* lx = lq + (size_t)spw * Q;      // own solution
-  double* lz = lx + (size_t)spw * Q;      // own z
-  double* lp = lz + (size_t)spw * Q;      // p over the window [w0, w1)
   const int nrow = ns * Q;
-
-  // --- global residual (Eq. 19, both norms) and stop test
-  double tot[NRM] = {0.0, 0.0, 0.0, 0.0};
-  for (int s = s0 + t; s < s1; s += COARSE_NT) {
-#pragma unroll
-    for (int v = 0; v < NRM; ++v) tot[v] += A.nrm[(size_t)s * NRM + v];
-  }
-  // consecutive grid sums alternate between two slots, so a slot is only
-  // rewritten after the barrier that follows every read of it
+  const unsigned spin = A.spin_limit;
+  const unsigned base = ctrl->bar_gen;
+  unsigned nsync = 0;
   int slot = 0;
-  if (!grid_sum<NRM>(tot, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
-  slot ^= 1;
-  const double R1 = tot[2] > 0.0 ? tot[0] / tot[2] : tot[0];
-  const double R2 = tot[3] > 0.0 ? sqrt(tot[1] / tot[3]) : sqrt(tot[1]);
-  const double R = fmax(R1, R2);
-  int status = -100;   // continue
-  if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2]) || !isfinite(tot[3])) status = -6;
-  else if (R <= A.rtol) status = 0;
-  else if (A.iter >= A.max_iters) status = -3;
-  if (w == 0 && t == 0) {
-    if (A.hist) A.hist[A.iter] = R;
-    ctrl->r1 = R1;
-    ctrl->r2 = R2;
-    if (status != -100) {
-      ctrl->status = status;
-      ctrl->iters = A.iter;
-      ctrl->done = 1;
-      ctrl->bar_gen = base + nsync;
-    }
+  const int wmax = min(M, spw + 2 * g.mx + 2);
+  double* lown = lds;                          // own rows of the vector being preconditioned
+  double* lw1 = lown + (size_t)spw * Q;        // window (first vector)
+  double* lw2 = lw1 + (size_t)wmax * Q;        // window (second vector)
+  double* lnext = lw2 + (size_t)wmax * Q;
+  const size_t r0 = (size_t)s0 * Q;            // first own row
+  // Own-row vectors, touched only by the owning thread: in LDS when they fit,
+  // else in global memory.  All are indexed from the workgroup's first row.
+  double *vx, *vr, *vu, *vw, *vz, *vq, *vs, *vp;
+  double* vn = A.cn + r0;
+  if (A.vec_lds) {
+    double* b = lnext;
+    vx = b; vr = b + (size_t)spw * Q; vu = b + 2 * (size_t)spw * Q; vw = b + 3 * (size_t)spw * Q;
+    vz = b + 4 * (size_t)spw * Q; vq = b + 5 * (size_t)spw * Q; vs = b + 6 * (size_t)spw * Q;
+    vp = b + 7 * (size_t)spw * Q;
+    lnext += 8 * (size_t)spw * Q;
+  } else {
+    vx = A.a + r0; vr = A.cr + r0; vu = A.cu + r0; vw = A.cw + r0; vz = A.cz + r0;
+    vq = A.cq + r0; vs = A.cs + r0; vp = A.cp + r0;
   }
-  if (status != -100) return;
-
-  // --- assemble each set's diagonal block and factor it (one thread per set)
-  for (int s = s0 + t; s < s1; s += COARSE_NT) {
-    double B[Q * Q];
-    const double* g1 = A.g1 + (size_t)s * 36;
-    const double* kr = A.krow + (size_t)s * KROW;
-#pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-      for (int l = 0; l < 6; ++l) B[m * Q + l] = g1[m * 6 + l];
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-      for (int l = 0; l < 6; ++l) { B[(6 + q) * Q + l] = kr[q * 9 + l]; B[l * Q + 6 + q] = kr[q * 9 + l]; }
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-      for (int p = 0; p < 3; ++p) B[(6 + q) * Q + 6 + p] = 0.5 * (kr[q * 9 + 6 + p] + kr[p * 9 + 6 + q]);
-    double* bd = A.bdiag + (size_t)s * Q * Q;
-#pragma unroll
-    for (int v = 0; v < Q * Q; ++v) bd[v] = B[v];
-    double sc[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) sc[k] = B[k * Q + k] > 0.0 ? 1.0 / sqrt(B[k * Q + k]) : 0.0;
-    double L[45];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      double dkk = sc[k] * sc[k] * B[k * Q + k];
-#pragma unroll
-      for (int j = 0; j < k; ++j) dkk -= L[lpk(k, j)] * L[lpk(k, j)];
-      const bool keep = sc[k] > 0.0 && dkk > 1e-9;
-      const double lkk = keep ? sqrt(dkk) : 0.0;
-      L[lpk(k, k)] = lkk;
-#pragma unroll
-      for (int i = k + 1; i < Q; ++i) {
-        double v = sc[i] * sc[k] * B[i * Q + k];
-#pragma unroll
-        for (int j = 0; j < k; ++j) v -= L[lpk(i, j)] * L[lpk(k, j)];
-        L[lpk(i, k)] = keep ? v / lkk : 0.0;
-      }
+  // own sets' blocks (diagonal, six neighbours, pseudo-inverse)
+  const double* bd = A.bdiag + (size_t)s0 * Q * Q;
+  const double* ob = A.off + (size_t)s0 * NDIR * Q * Q;
+  const double* bi = A.binv + (size_t)s0 * Q * Q;
+  if (A.blk_lds) {
+    double* lb = lnext;
+    for (int e = t; e < ns * Q * Q; e += COARSE_NT) {
+      lb[e] = bd[e];
+      lb[(size_t)spw * Q * Q + e] = bi[e];
     }
-#pragma unroll
-    for (int v = 0; v < 45; ++v) A.lfac[(size_t)s * 45 + v] = L[v];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) A.bscale[(size_t)s * Q + k] = sc[k];
+    double* lo = lb + 2 * (size_t)spw * Q * Q;
+    for (int e = t; e < ns * NDIR * Q * Q; e += COARSE_NT) lo[e] = ob[e];
+    bd = lb;
+    bi = lb + (size_t)spw * Q * Q;
+    ob = lo;
+    __syncthreads();
   }
-  __syncthreads();
 
-  // --- start: a = 0, or (warm start) the previous coefficients scaled by
-  //     the step that minimises the upper-level energy along them, which
-  //     keeps the energy decrease of the outer iteration.
+  // --- start.  The warm start x0 = theta a_prev takes the previous solve's
+  //     coefficients scaled by the step that minimises the upper-level
+  //     energy along them (so the outer energy still decreases).  With
+  //     y = K_a a_prev:  r0 = P - theta y,  u0 = B^+ P - theta B^+ y, and
+  //     theta = (a_prev . P) / (a_prev . y).  One grid sum carries theta's
+  //     two dot products, the stop test's four norm sums, and orders the
+  //     publication of B^+ P and B^+ y.
   const bool warm = A.warm && A.iter > 0;
-  for (int e = t; e < nrow; e += COARSE_NT) {
-    lr[e] = A.force[(size_t)s0 * Q + e];
-    lx[e] = warm ? A.a[(size_t)s0 * Q + e] : 0.0;
+  for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = warm ? A.a[(size_t)w0 * Q + e] : 0.0;
+  __syncthreads();
+  double red6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int s = s0 + t; s < s1; s += COARSE_NT) {
+#pragma unroll
+    for (int v = 0; v < NRM; ++v) red6[v] += A.nrm[(size_t)s * NRM + v];
   }
-  if (warm) {
-    for (int e = t; e < win * Q; e += COARSE_NT) lp[e] = A.a[(size_t)w0 * Q + e];
-    __syncthreads();
-    double nd[2] = {0.0, 0.0};
-    for (int e = t; e < nrow; e += COARSE_NT) {
-      const double q = coarse_row(g, A, s0 + e / Q, e % Q, lp, w0);
-      lq[e] = q;
-      nd[0] += lx[e] * lr[e];
-      nd[1] += lx[e] * q;
-    }
-    if (!grid_sum<2>(nd, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
-    slot ^= 1;
-    const double th = (nd[1] > 0.0 && nd[0] > 0.0) ? nd[0] / nd[1] : 0.0;
-    for (int e = t; e < nrow; e += COARSE_NT) {
-      lx[e] *= th;
-      lr[e] -= th * lq[e];
-    }
+  for (int e = t; e < nrow; e += COARSE_NT) {
+    const int s = s0 + e / Q, m = e % Q;
+    const double y = warm ? coarse_row(g, bd, ob, s, s0, m, lw1, w0) : 0.0;
+    const double aprev = lw1[(size_t)(s0 - w0) * Q + e];
+    red6[4] += aprev * A.force[r0 + e];
+    red6[5] += aprev * y;
+    vn[e] = y;                   // keep y for r0
+    lown[e] = A.force[r0 + e];
   }
   __syncthreads();
-  double rz_v[1] = {0.0};
-  for (int s = s0 + t; s < s1; s += COARSE_NT) {
-    double zv[Q];
-    const int o = (s - s0) * Q;
-    block_apply(A.lfac + (size_t)s * 45, A.bscale + (size_t)s * Q, lr + o, zv);
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      lz[o + k] = zv[k];
-      pub_store(&A.cz[(size_t)s * Q + k], zv[k]);
-      rz_v[0] += lr[o + k] * zv[k];
-    }
+  for (int e = t; e < nrow; e += COARSE_NT) {
+    const int s = s0 + e / Q, m = e % Q;
+    const double v = pinv_row(bi, s, s0, m, lown);
+    pub_store(&A.pub0[r0 + e], v);    // B^+ P
+    vz[e] = v;
   }
-  if (!grid_sum<1>(rz_v, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
+  __syncthreads();
+  for (int e = t; e < nrow; e += COARSE_NT) lown[e] = vn[e];
+  __syncthreads();
+  for (int e = t; e < nrow; e += COARSE_NT) {
+    const int s = s0 + e / Q, m = e % Q;
+    const double v = pinv_row(bi, s, s0, m, lown);
+    pub_store(&A.pub1[r0 + e], v);    // B^+ y
+    vq[e] = v;
+  }
+  if (!grid_publish_wait<6>(red6, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot, sv))
+    return;
+  grid_collect<6>(A.red, slot, nwg, sv);
   slot ^= 1;
-  double rz = rz_v[0];
-  const double rz0 = rz;
-  double beta = 0.0;
-  int it = 0;
-  double* pprev = A.cp0;
-  double* pcur = A.cp1;
-  for (; it < A.coarse_iters; ++it) {
-    if (!(rz > A.coarse_rtol * A.coarse_rtol * rz0) || !(rz > 0.0)) break;
-    // p = z + beta p_prev over the window; own entries are published
-    for (int e = t; e < win * Q; e += COARSE_NT) {
-      const size_t ge = (size_t)w0 * Q + e;
-      const double pv = beta != 0.0 ? pub_load(&A.cz[ge]) + beta * pub_load(&pprev[ge])
-                                     : pub_load(&A.cz[ge]);
-      lp[e] = pv;
-      if (ge >= (size_t)s0 * Q && ge < (size_t)s1 * Q) pub_store(&pcur[ge], pv);
-    }
-    __syncthreads();
-    double pq_v[1] = {0.0};
-    for (int e = t; e < nrow; e += COARSE_NT) {
-      const double q = coarse_row(g, A, s0 + e / Q, e % Q, lp, w0);
-      lq[e] = q;
-      pq_v[0] += lp[(size_t)(s0 - w0) * Q + e] * q;
-    }
-    if (!grid_sum<1>(pq_v, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
-    slot ^= 1;
-    const double alpha = pq_v[0] > 0.0 ? rz / pq_v[0] : 0.0;
-    for (int e = t; e < nrow; e += COARSE_NT) {
-      lx[e] += alpha * lp[(size_t)(s0 - w0) * Q + e];
-      lr[e] -= alpha * lq[e];
-    }
-    __syncthreads();
-    double rzn_v[1] = {0.0};
-    for (int s = s0 + t; s < s1; s += COARSE_NT) {
-      double zv[Q];
-      const int o = (s - s0) * Q;
-      block_apply(A.lfac + (size_t)s * 45, A.bscale + (size_t)s * Q, lr + o, zv);
+  __syncthreads();
 #pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        lz[o + k] = zv[k];
-        pub_store(&A.cz[(size_t)s * Q + k], zv[k]);
-        rzn_v[0] += lr[o + k] * zv[k];
+  for (int v = 0; v < 6; ++v) red6[v] = sv[v];
+  {
+    const double R1 = red6[2] > 0.0 ? red6[0] / red6[2] : red6[0];
+    const double R2 = red6[3] > 0.0 ? sqrt(red6[1] / red6[3]) : sqrt(red6[1]);
+    const double R = fmax(R1, R2);
+    int status = -100;   // continue
+    if (!isfinite(red6[0]) || !isfinite(red6[1]) || !isfinite(red6[2]) || !isfinite(red6[3])) status = -6;
+    else if (R <= A.rtol) status = 0;
+    else if (A.iter >= A.max_iters) status = -3;
+    if (w == 0 && t == 0) {
+      if (A.hist) A.hist[A.iter] = R;
+      ctrl->r1 = R1;
+      ctrl->r2 = R2;
+      if (status != -100) {
+        ctrl->status = status;
+        ctrl->iters = A.iter;
+        ctrl->done = 1;
+        ctrl->bar_gen = base + nsync;
       }
     }
-    if (!grid_sum<1>(rzn_v, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot)) return;
-    slot ^= 1;
-    beta = rz > 0.0 ? rzn_v[0] / rz : 0.0;
-    rz = rzn_v[0];
-    double* tmp = pprev; pprev = pcur; pcur = tmp;
+    if (status != -100) return;
   }
-  for (int e = t; e < nrow; e += COARSE_NT) A.a[(size_t)s0 * Q + e] = lx[e];
+  const double theta = (warm && red6[5] > 0.0 && red6[4] > 0.0) ? red6[4] / red6[5] : 0.0;
+  // x0, r0, u0 (own) and u0 over the window, then w0 = K_a u0
+  for (int e = t; e < win * Q; e += COARSE_NT) {
+    const size_t ge = (size_t)w0 * Q + e;
+    lw2[e] = pub_load(&A.pub0[ge]) - theta * pub_load(&A.pub1[ge]);
+  }
+  for (int e = t; e < nrow; e += COARSE_NT) {
+    vx[e] = theta * lw1[(size_t)(s0 - w0) * Q + e];
+    vr[e] = A.force[r0 + e] - theta * vn[e];
+    vu[e] = vz[e] - theta * vq[e];
+  }
+  __syncthreads();
+  for (int e = t; e < nrow; e += COARSE_NT) {
+    const double wv = coarse_row(g, bd, ob, s0 + e / Q, s0, e % Q, lw2, w0);
+    vw[e] = wv;
+    vz[e] = 0.0;
+    vq[e] = 0.0;
+    vs[e] = 0.0;
+    vp[e] = 0.0;
+  }
+  __syncthreads();
+
+  // --- pipelined PCG iterations
+  double gamma0 = 0.0, gamma_prev = 0.0, alpha_prev = 0.0;
+  int it = 0;
+  if (nrow <= COARSE_NT) {
+    // One row per thread: the row's blocks, pseudo-inverse row and PCG
+    // vectors live in registers; only the neighbour window is read from LDS.
+    const bool own = t < nrow;
+    const int s = s0 + (own ? t / Q : 0), m = t % Q;
+    const int I = s % g.mx, J = s / g.mx;
+    double brow[Q], birow[Q], orow[NDIR][Q];
+    int noff[NDIR];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      brow[l] = own ? bd[(size_t)(s - s0) * Q * Q + m * Q + l] : 0.0;
+      birow[l] = own ? bi[(size_t)(s - s0) * Q * Q + m * Q + l] : 0.0;
+    }
+#pragma unroll
+    for (int dir = 0; dir < NDIR; ++dir) {
+      const int I2 = I + nb_di(dir), J2 = J + nb_dj(dir);
+      const bool ok = own && I2 >= 0 && I2 < g.mx && J2 >= 0 && J2 < g.my;
+      noff[dir] = ok ? (J2 * g.mx + I2 - w0) * Q : (s - w0) * Q;
+#pragma unroll
+      for (int l = 0; l < Q; ++l)
+        orow[dir][l] = ok ? ob[((size_t)(s - s0) * NDIR + dir) * Q * Q + m * Q + l] : 0.0;
+    }
+    const int sown = (s - w0) * Q, sset = (s - s0) * Q;
+    double x = own ? vx[t] : 0.0, r = own ? vr[t] : 0.0, u = own ? vu[t] : 0.0;
+    double wv = own ? vw[t] : 0.0, z = 0.0, q = 0.0, sv_ = 0.0, p = 0.0;
+    for (;; ++it) {
+      double gd[2] = {r * u, wv * u};
+      if (own) lown[t] = wv;
+      __syncthreads();
+      double mv = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) mv += birow[l] * lown[sset + l];
+      double* mpub = (it & 1) ? A.pub1 : A.pub0;
+      if (own) {
+        if (nwg == 1) lw1[t] = mv;
+        else pub_store(&mpub[r0 + t], mv);
+      }
+      if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot, sv))
+        return;
+      grid_collect<2>(A.red, slot, nwg, sv);
+      if (nwg > 1)
+        for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = pub_load(&mpub[(size_t)w0 * Q + e]);
+      slot ^= 1;
+      __syncthreads();
+      const double gamma = sv[0], delta = sv[1];
+      if (it == 0) gamma0 = gamma;
+      if (it >= A.coarse_iters || !(gamma > 0.0) ||
+          !(gamma > A.coarse_rtol * A.coarse_rtol * gamma0)) break;
+      double alpha, beta;
+      if (it == 0) {
+        beta = 0.0;
+        alpha = delta > 0.0 ? gamma / delta : 0.0;
+      } else {
+        beta = gamma / gamma_prev;
+        const double den = delta - beta * gamma / alpha_prev;
+        alpha = den > 0.0 ? gamma / den : 0.0;
+      }
+      if (!(alpha > 0.0)) break;
+      double n = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) n += brow[l] * lw1[sown + l];
+#pragma unroll
+      for (int dir = 0; dir < NDIR; ++dir)
+#pragma unroll
+        for (int l = 0; l < Q; ++l) n += orow[dir][l] * lw1[noff[dir] + l];
+      const double mm = lw1[sown + m];
+      z = n + beta * z;
+      q = mm + beta * q;
+      sv_ = wv + beta * sv_;
+      p = u + beta * p;
+      x += alpha * p;
+      r -= alpha * sv_;
+      u -= alpha * q;
+      wv -= alpha * z;
+      gamma_prev = gamma;
+      alpha_prev = alpha;
+      __syncthreads();
+    }
+    if (own) vx[t] = x;
+  } else
+  for (;; ++it) {
+    // dot products of this iteration, and m = B^+ w published for the neighbours
+    double gd[2] = {0.0, 0.0};
+    for (int e = t; e < nrow; e += COARSE_NT) {
+      const double u = vu[e], wv = vw[e];
+      gd[0] += vr[e] * u;
+      gd[1] += wv * u;
+      lown[e] = wv;
+    }
+    __syncthreads();
+    double* mpub = (it & 1) ? A.pub1 : A.pub0;
+    for (int e = t; e < nrow; e += COARSE_NT) {
+      const double mv = pinv_row(bi, s0 + e / Q, s0, e % Q, lown);
+      if (nwg == 1) lw1[e] = mv;            // one workgroup: the window is its own sets
+      else pub_store(&mpub[r0 + e], mv);
+    }
+    if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot, sv))
+      return;
+    // one round trip: the partial sums and the neighbours' m together
+    grid_collect<2>(A.red, slot, nwg, sv);
+    if (nwg > 1)
+      for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = pub_load(&mpub[(size_t)w0 * Q + e]);
+    slot ^= 1;
+    __syncthreads();
+    const double gamma = sv[0], delta = sv[1];
+    if (it == 0) gamma0 = gamma;
+    if (it >= A.coarse_iters || !(gamma > 0.0) ||
+        !(gamma > A.coarse_rtol * A.coarse_rtol * gamma0)) break;
+    double alpha, beta;
+    if (it == 0) {
+      beta = 0.0;
+      alpha = delta > 0.0 ? gamma / delta : 0.0;
+    } else {
+      beta = gamma / gamma_prev;
+      const double den = delta - beta * gamma / alpha_prev;
+      alpha = den > 0.0 ? gamma / den : 0.0;
+    }
+    if (!(alpha > 0.0)) break;
+    for (int e = t; e < nrow; e += COARSE_NT) {
+      const double n = coarse_row(g, bd, ob, s0 + e / Q, s0, e % Q, lw1, w0);
+      const double m = lw1[(size_t)(s0 - w0) * Q + e];
+      const double z = n + beta * vz[e];
+      const double q = m + beta * vq[e];
+      const double sv = vw[e] + beta * vs[e];
+      const double p = vu[e] + beta * vp[e];
+      vz[e] = z; vq[e] = q; vs[e] = sv; vp[e] = p;
+      vx[e] += alpha * p;
+      vr[e] -= alpha * sv;
+      vu[e] -= alpha * q;
+      vw[e] -= alpha * z;
+    }
+    gamma_prev = gamma;
+    alpha_prev = alpha;
+    __syncthreads();
+  }
+  if (A.vec_lds)
+    for (int e = t; e < nrow; e += COARSE_NT) A.a[r0 + e] = vx[e];
   if (w == 0 && t == 0) {
     ctrl->coarse_iters += it;
     ctrl->bar_gen = base + nsync;
@@ -812,7 +993,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   if (A.tr_force)
     for (size_t e = (size_t)s0 * Q + t; e < (size_t)s1 * Q; e += COARSE_NT) A.tr_force[e] = A.force[e];
   if (A.tr_coef)
-    for (int e = t; e < nrow; e += COARSE_NT) A.tr_coef[(size_t)s0 * Q + e] = lx[e];
+    for (int e = t; e < nrow; e += COARSE_NT) A.tr_coef[r0 + e] = A.a[r0 + e];
 }
 
 // ---------------------------------------------------------------------------
@@ -1083,7 +1264,7 @@ hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream) 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  const size_t lds = coarse_lds_bytes(g, a.nwg);
+  const size_t lds = coarse_lds_bytes(g, a.nwg, a.vec_lds, a.blk_lds);
   if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_coarse, dim3(a.nwg), dim3(COARSE_NT), lds, stream, g, a);
   return hipGetLastError();

@@ -22,8 +22,9 @@ struct Work {
   double2* u[2] = {nullptr, nullptr};
   void* d[2] = {nullptr, nullptr};
   double *a = nullptr, *krow = nullptr, *force = nullptr, *nrm = nullptr, *off = nullptr;
-  double *bdiag = nullptr, *lfac = nullptr, *bscale = nullptr;
-  double *cr = nullptr, *cz = nullptr, *cp0 = nullptr, *cp1 = nullptr, *cq = nullptr;
+  double *bdiag = nullptr, *binv = nullptr;
+  double *cr = nullptr, *cu = nullptr, *cw = nullptr, *cz = nullptr, *cq = nullptr;
+  double *cs = nullptr, *cp = nullptr, *cn = nullptr, *pub0 = nullptr, *pub1 = nullptr;
   double *red = nullptr, *hist = nullptr;
   Ctrl* ctrl = nullptr;
   unsigned* flags = nullptr;       // grid-sum arrival flags of the upper-level kernel
@@ -71,7 +72,10 @@ int default_set_edge(int nx, int ny);
 Geo make_geo(int nx, int ny, int E);
 size_t padded_nodes(const Geo& g);
 size_t work_bytes(const Geo& g, bool mixed, int hist_cap);
-int coarse_workgroups(const Geo& g);
+struct CoarseShape {
+  int nwg, vec_lds, blk_lds;
+};
+CoarseShape coarse_shape(const Geo& g);
 void resolve_opts(const tl_opts* o, Opts* r);
 tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f, int k,
                             hipStream_t st, hipEvent_t* ev = nullptr);
