@@ -126,7 +126,7 @@ tl_status Work::alloc(const Geo& g_, bool mixed_, int hist_cap_) {
 constexpr size_t kCoarseLdsCap = 150 * 1024;
 
 CoarseShape coarse_shape(const Geo& g) {
-  const int per = std::max(1, env_int("TL_COARSE_SETS_PER_WG", 8));
+  const int per = std::max(1, env_int("TL_COARSE_SETS_PER_WG", 16));
   CoarseShape c;
   c.nwg = std::max(1, std::min((g.M + per - 1) / per, COARSE_MAX_WG));
   while (c.nwg < COARSE_MAX_WG && coarse_lds_bytes(g, c.nwg, 0, 0) > kCoarseLdsCap) ++c.nwg;
@@ -141,8 +141,8 @@ void resolve_opts(const tl_opts* o, Opts* r) {
   r->rtol = o && o->rtol > 0.0 ? o->rtol : 1e-8;
   r->max_iters = o && o->max_iters > 0 ? o->max_iters : 20000;
   r->inner = o && o->inner_iters > 0 ? o->inner_iters : 10;
-  r->coarse_iters = o && o->coarse_iters > 0 ? o->coarse_iters : 40;
-  r->coarse_rtol = o && o->coarse_rtol > 0.0 ? o->coarse_rtol : 1e-4;
+  r->coarse_iters = o && o->coarse_iters > 0 ? o->coarse_iters : 300;
+  r->coarse_rtol = o && o->coarse_rtol > 0.0 ? o->coarse_rtol : 0.1;
   r->warm = o ? o->warm_start : 0;
   r->trace = o ? o->trace : nullptr;
   r->profile = o ? o->profile : 0;
@@ -170,12 +170,15 @@ tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const d
   OffArgs oa;
   oa.d = w->d[(k + 1) & 1];
   oa.off = w->off;
-  oa.g1 = L->g1;
-  oa.krow = w->krow;
-  oa.bdiag = w->bdiag;
-  oa.binv = w->binv;
   oa.ctrl = w->ctrl;
   TL_TRY(launch_offdiag(o.mixed, L->g, L->ea, L->mask, oa, st));
+  BlockArgs ba;
+  ba.g1 = L->g1;
+  ba.krow = w->krow;
+  ba.bdiag = w->bdiag;
+  ba.binv = w->binv;
+  ba.ctrl = w->ctrl;
+  TL_TRY(launch_blockinv(L->g, ba, st));
   if (ev) TL_TRY(hipEventRecord(ev[2], st));
   CoarseArgs ca;
   ca.g1 = L->g1;

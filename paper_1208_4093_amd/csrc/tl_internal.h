@@ -112,6 +112,10 @@ struct CoarseArgs {
 struct OffArgs {
   const void* d;         // T2 padded relaxation increments of this iteration
   double* off;           // [M][6][81]
+  const Ctrl* ctrl;
+};
+
+struct BlockArgs {
   const double* g1;      // [M][36]
   const double* krow;    // [M][27]
   double* bdiag;         // [M][81] assembled diagonal blocks
@@ -124,6 +128,7 @@ hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t*
                        const TileArgs& a, hipStream_t stream);
 hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
                           const OffArgs& a, hipStream_t stream);
+hipError_t launch_blockinv(const Geo& g, const BlockArgs& a, hipStream_t stream);
 hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream);
 size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds);
 hipError_t launch_group1(const Geo& g, const float* ea, const uint8_t* mask, double* g1,

@@ -526,25 +526,33 @@ __global__ __launch_bounds__(256) void k_offdiag(Geo g, const float* __restrict_
     }
     __syncthreads();
   }
-  // the set's diagonal block (constant translation/gradient part + the rows
-  // of the relaxation modes from the tile kernel) and its pseudo-inverse
-  if (t == 0) {
-    double B[Q * Q];
-    const double* g1 = A.g1 + (size_t)s * 36;
-    const double* kr = A.krow + (size_t)s * KROW;
-    for (int m = 0; m < 6; ++m)
-      for (int l = 0; l < 6; ++l) B[m * Q + l] = g1[m * 6 + l];
-    for (int q = 0; q < 3; ++q)
-      for (int l = 0; l < 6; ++l) { B[(6 + q) * Q + l] = kr[q * 9 + l]; B[l * Q + 6 + q] = kr[q * 9 + l]; }
-    for (int q = 0; q < 3; ++q)
-      for (int p = 0; p < 3; ++p) B[(6 + q) * Q + 6 + p] = 0.5 * (kr[q * 9 + 6 + p] + kr[p * 9 + 6 + q]);
-    double* bd = A.bdiag + (size_t)s * Q * Q;
-    for (int v = 0; v < Q * Q; ++v) bd[v] = B[v];
-    double Bi[Q * Q];
-    block_pinv(B, Bi);
-    double* bi = A.binv + (size_t)s * Q * Q;
-    for (int v = 0; v < Q * Q; ++v) bi[v] = Bi[v];
-  }
+}
+
+// ---------------------------------------------------------------------------
+// Each set's diagonal upper-level block: the constant translation/gradient
+// part plus the rows of the relaxation modes from the tile kernel (Eq. 6),
+// and its pseudo-inverse for the block-Jacobi preconditioner.  One thread
+// per set.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_blockinv(Geo g, BlockArgs A) {
+  if (A.ctrl->done) return;
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= g.M) return;
+  double B[Q * Q];
+  const double* g1 = A.g1 + (size_t)s * 36;
+  const double* kr = A.krow + (size_t)s * KROW;
+  for (int m = 0; m < 6; ++m)
+    for (int l = 0; l < 6; ++l) B[m * Q + l] = g1[m * 6 + l];
+  for (int q = 0; q < 3; ++q)
+    for (int l = 0; l < 6; ++l) { B[(6 + q) * Q + l] = kr[q * 9 + l]; B[l * Q + 6 + q] = kr[q * 9 + l]; }
+  for (int q = 0; q < 3; ++q)
+    for (int p = 0; p < 3; ++p) B[(6 + q) * Q + 6 + p] = 0.5 * (kr[q * 9 + 6 + p] + kr[p * 9 + 6 + q]);
+  double* bd = A.bdiag + (size_t)s * Q * Q;
+  for (int v = 0; v < Q * Q; ++v) bd[v] = B[v];
+  double Bi[Q * Q];
+  block_pinv(B, Bi);
+  double* bi = A.binv + (size_t)s * Q * Q;
+  for (int v = 0; v < Q * Q; ++v) bi[v] = Bi[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -1253,6 +1261,11 @@ hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8
                           const OffArgs& a, hipStream_t stream) {
   if (mixed) hipLaunchKernelGGL(k_offdiag<float>, dim3(g.M), dim3(256), 0, stream, g, ea, mask, a);
   else hipLaunchKernelGGL(k_offdiag<double>, dim3(g.M), dim3(256), 0, stream, g, ea, mask, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_blockinv(const Geo& g, const BlockArgs& a, hipStream_t stream) {
+  hipLaunchKernelGGL(k_blockinv, dim3((g.M + 63) / 64), dim3(64), 0, stream, g, a);
   return hipGetLastError();
 }
 
