@@ -54,7 +54,7 @@ Geo make_geo(int nx, int ny, int E) {
   Geo g;
   g.nx = nx;
   g.ny = ny;
-  g.pitch = ((nx + 2 + 15) / 16) * 16;
+  g.pitch = ((nx + LPAD + 1 + 31) / 32) * 32;
   g.E = E;
   g.mx = (nx + E - 1) / E;
   g.my = (ny + E - 1) / E;

@@ -2,7 +2,7 @@
 //
 // Device layout of one lattice (nx x ny nodes, set edge E):
 //   * node arrays are padded with a one-node ring: node (i, j), -1 <= i <= nx,
-//     -1 <= j <= ny, lives at (j + 1) * pitch + (i + 1).  The ring is clamped
+//     -1 <= j <= ny, lives at (j + 1) * pitch + (i + LPAD).  The ring is clamped
 //     (mask 1), carries zero rod stiffness and zero displacement, so stencil
 //     and halo loads never leave the allocation and need no bounds tests;
 //   * ea      : float  [3][ny + 2][pitch]   rod EA of the three forward rods;
@@ -30,6 +30,8 @@ constexpr int TILE_OUT = KROW + Q + NRM;
 constexpr int COARSE_NT = 256;  // threads per upper-level workgroup
 constexpr int COARSE_MAX_WG = 256;
 constexpr int REDW = 8;         // values per workgroup and slot of a grid sum
+constexpr int LPAD = 32;        // left padding (elements) of node arrays: interior
+                                // rows start on a 128-byte boundary for every type
 
 // Set-grid neighbour offsets (dI, dJ); direction d and d + 3 are opposite.
 __host__ __device__ constexpr int nb_di(int d) { return d == 0 ? 1 : d == 2 ? -1 : d == 3 ? -1 : d == 5 ? 1 : 0; }

@@ -17,6 +17,7 @@
 #include "tl_internal.h"
 
 #include <math.h>
+#include <stdlib.h>
 
 #include <algorithm>
 
@@ -27,7 +28,7 @@ namespace {
 constexpr double kS3 = 0.86602540378443864676;   // sqrt(3)/2, y-step of a lattice row
 
 __device__ __forceinline__ size_t pidx(const Geo& g, int i, int j) {
-  return (size_t)(j + 1) * g.pitch + (size_t)(i + 1);
+  return (size_t)(j + 1) * g.pitch + (size_t)(i + LPAD);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -76,6 +77,27 @@ __device__ __forceinline__ T block_sum(T v, double* slot) {
 #pragma unroll
   for (int w = 0; w < NW; ++w) s += slot[w];
   return (T)s;
+}
+
+// Workgroup sum of two values with one barrier; `slot` holds 2 entries per
+// wave and must not be reused before the next barrier.
+template <int NW>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* slot) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    slot[2 * (threadIdx.x >> 6)] = a;
+    slot[2 * (threadIdx.x >> 6) + 1] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    sa += slot[2 * w];
+    sb += slot[2 * w + 1];
+  }
+  a = sa;
+  b = sb;
 }
 
 template <typename T> __device__ __forceinline__ typename V2<T>::type mk2(T x, T y);
@@ -1238,21 +1260,35 @@ int grid_for(size_t n, int nt, int cap) {
 }
 }  // namespace
 
+// Threads per tile workgroup for each set edge and precision (measured:
+// 256 for E = 32; 512 for E = 64 in float32, 1024 in float64, where 512
+// threads spill).  TL_TILE_THREADS overrides for tuning.
+static int tile_threads(int E, bool mixed) {
+  const char* v = getenv("TL_TILE_THREADS");
+  const int env = v && *v ? atoi(v) : 0;
+  if (E == 16) return 256;
+  if (E == 32) return env == 256 || env == 512 ? env : 256;
+  return env == 512 || env == 1024 ? env : (mixed ? 512 : 1024);
+}
+
 hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
                        const TileArgs& a, hipStream_t stream) {
   const dim3 grid(g.M);
+  const int nt = tile_threads(g.E, mixed);
 #define TL_TILE(T, E, NT) hipLaunchKernelGGL((k_tile<T, E, NT>), grid, dim3(NT), 0, stream, g, ea, mask, a)
+#define TL_TILE_ALL(T)                                   \
+  if (g.E == 16) TL_TILE(T, 16, 256);                    \
+  else if (g.E == 32 && nt == 256) TL_TILE(T, 32, 256);  \
+  else if (g.E == 32) TL_TILE(T, 32, 512);               \
+  else if (g.E == 64 && nt == 512) TL_TILE(T, 64, 512);  \
+  else if (g.E == 64) TL_TILE(T, 64, 1024);              \
+  else return hipErrorInvalidValue;
   if (mixed) {
-    if (g.E == 16) TL_TILE(float, 16, 256);
-    else if (g.E == 32) TL_TILE(float, 32, 256);
-    else if (g.E == 64) TL_TILE(float, 64, 1024);
-    else return hipErrorInvalidValue;
+    TL_TILE_ALL(float)
   } else {
-    if (g.E == 16) TL_TILE(double, 16, 256);
-    else if (g.E == 32) TL_TILE(double, 32, 256);
-    else if (g.E == 64) TL_TILE(double, 64, 1024);
-    else return hipErrorInvalidValue;
+    TL_TILE_ALL(double)
   }
+#undef TL_TILE_ALL
 #undef TL_TILE
   return hipGetLastError();
 }
