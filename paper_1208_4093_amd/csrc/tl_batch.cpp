@@ -1,12 +1,20 @@
-// Batched solves and the continuous-batching server.
+// Batched solves and the continuous-batching server, on fused launches.
 //
-// Both advance a set of independent solves together, a round of outer
-// iterations at a time, on one stream: every live solve enqueues its next
-// iterations, one device-to-host copy per solve reads the stop flags, and
-// finished solves are retired (their result copied out and certified).  The
-// server admits queued requests between rounds while the device state of the
-// admitted requests fits the HBM budget, so requests that arrive while
-// others run join the next round.
+// A FusedBatch advances several independent solves together.  One outer
+// iteration of all of them is: one tile launch per set edge present (the
+// tiles of every lattice with that edge), one boundary-block launch and one
+// block-inverse launch over the sets of all lattices, and one persistent
+// upper-level launch in which each lattice owns a range of co-resident
+// workgroups and runs its own grid sums.  Every kernel reads its lattice's
+// iteration counter and stop flag from device memory, so the launches of a
+// chunk of iterations have fixed arguments: tl_solve_batch captures one
+// chunk in a hipGraph and replays it.  Finished lattices' workgroups return
+// at once.  After each chunk a small kernel gathers every lattice's control
+// block into one array that is copied to the host in one transfer.
+//
+// The server keeps one FusedBatch of the admitted requests and rebuilds its
+// tables whenever a request is admitted or retired, so requests that arrive
+// while others run join at the next chunk boundary (continuous batching).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,15 +38,23 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+tl_status hip_status(hipError_t e) {
+  return e == hipSuccess ? TL_OK : e == hipErrorOutOfMemory ? TL_E_NOMEM : TL_E_DEVICE;
+}
+
+#define TB_TRY(expr)                             \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_status(e_); \
+  } while (0)
+
 struct Job {
   tl_lattice* L = nullptr;
   const double* f = nullptr;
   double* u = nullptr;
   Opts o{};
   Work* w = nullptr;
-  bool own_work = false;
-  int k = 0;                 // next outer iteration to enqueue
-  bool live = false;
+  bool own_work = true;
   tl_status status = TL_OK;
   tl_info info{};
   uint64_t ticket = 0;
@@ -47,24 +63,179 @@ struct Job {
   bool lock_lattice = true;  // false when the caller already holds the lattice lock
 };
 
-tl_status hip_status(hipError_t e) {
-  return e == hipSuccess ? TL_OK : e == hipErrorOutOfMemory ? TL_E_NOMEM : TL_E_DEVICE;
+// Device tables of one fused batch.
+struct FusedBatch {
+  std::vector<Job*> jobs;
+  std::vector<BatchEntry> h;
+  BatchEntry* d_entries = nullptr;
+  int* d_tile_lat[3] = {nullptr, nullptr, nullptr};   // set edges 16, 32, 64
+  int ntiles[3] = {0, 0, 0};
+  int* d_set_lat = nullptr;
+  int nsets = 0;
+  int* d_wg_lat = nullptr;
+  int nwg = 0;
+  size_t lds = 0;
+  Ctrl* d_ctrl = nullptr;       // gathered control blocks
+  Ctrl* h_ctrl = nullptr;       // pinned
+  int cap = 0;                  // entries the ctrl buffers can hold
+  bool mixed = false;
+
+  void release_tables() {
+    for (void* p : {(void*)d_entries, (void*)d_tile_lat[0], (void*)d_tile_lat[1],
+                    (void*)d_tile_lat[2], (void*)d_set_lat, (void*)d_wg_lat})
+      if (p) (void)hipFree(p);
+    d_entries = nullptr;
+    d_tile_lat[0] = d_tile_lat[1] = d_tile_lat[2] = nullptr;
+    d_set_lat = d_wg_lat = nullptr;
+  }
+  void release() {
+    release_tables();
+    if (d_ctrl) (void)hipFree(d_ctrl);
+    if (h_ctrl) (void)hipHostFree(h_ctrl);
+    d_ctrl = nullptr;
+    h_ctrl = nullptr;
+    cap = 0;
+  }
+
+  static int edge_slot(int E) { return E == 16 ? 0 : E == 32 ? 1 : 2; }
+
+  // Build the entry and lookup tables for the current jobs (all of whose
+  // work spaces exist and were initialised).
+  tl_status build(hipStream_t st) {
+    release_tables();
+    const int n = (int)jobs.size();
+    if (n == 0) return TL_OK;
+    mixed = jobs[0]->o.mixed;
+    h.assign(n, BatchEntry{});
+    std::vector<int> tl[3], sl;
+    // upper-level workgroups: one each, then the rest of the co-resident
+    // capacity to the lattices with the most sets, within their own shape
+    std::vector<CoarseShape> shape(n);
+    std::vector<int> nw(n, 1);
+    for (int b = 0; b < n; ++b) shape[b] = coarse_shape(jobs[b]->L->g);
+    // co-resident workgroups at the LDS budget used below (80 KB: two per CU)
+    const int capacity = coarse_batch_capacity(80 * 1024);
+    if (capacity < n) return TL_E_DEVICE;
+    int used = n;
+    std::vector<int> order(n);
+    for (int b = 0; b < n; ++b) order[b] = b;
+    std::sort(order.begin(), order.end(),
+              [&](int x, int y) { return jobs[x]->L->g.M > jobs[y]->L->g.M; });
+    bool grew = true;
+    while (grew && used < capacity) {
+      grew = false;
+      for (int b : order) {
+        if (used >= capacity) break;
+        if (nw[b] < shape[b].nwg) { ++nw[b]; ++used; grew = true; }
+      }
+    }
+    // with fewer workgroups than the single-lattice shape, LDS staging may
+    // no longer fit: decide per lattice, then size the launch's LDS
+    size_t lds_need = 0;
+    for (int b = 0; b < n; ++b) {
+      const Geo& g = jobs[b]->L->g;
+      if (coarse_lds_bytes(g, nw[b], 0, 0) > 150 * 1024) return TL_E_INVAL;
+      const int vec = coarse_lds_bytes(g, nw[b], 1, 0) <= 80 * 1024;
+      const int blk = vec && coarse_lds_bytes(g, nw[b], 1, 1) <= 80 * 1024;
+      shape[b].vec_lds = vec;
+      shape[b].blk_lds = blk;
+      lds_need = std::max(lds_need, coarse_lds_bytes(g, nw[b], vec, blk));
+    }
+    if (coarse_batch_capacity(lds_need) < used) {
+      // a larger LDS lowered the occupancy: drop the staging everywhere
+      lds_need = 0;
+      for (int b = 0; b < n; ++b) {
+        shape[b].vec_lds = shape[b].blk_lds = 0;
+        lds_need = std::max(lds_need, coarse_lds_bytes(jobs[b]->L->g, nw[b], 0, 0));
+      }
+      if (coarse_batch_capacity(lds_need) < used) return TL_E_DEVICE;
+    }
+    lds = lds_need;
+    std::vector<int> wl;
+    nsets = 0;
+    for (int b = 0; b < n; ++b) {
+      Job* j = jobs[b];
+      const Geo& g = j->L->g;
+      BatchEntry& e = h[b];
+      e.g = g;
+      e.ea = j->L->ea;
+      e.mask = j->L->mask;
+      make_iteration_args(j->L, j->w, j->o, j->f, &e.ta, &e.oa, &e.ba, &e.ca);
+      e.ca.nwg = nw[b];
+      e.ca.vec_lds = shape[b].vec_lds;
+      e.ca.blk_lds = shape[b].blk_lds;
+      const int slot = edge_slot(g.E);
+      e.tile0 = (int)tl[slot].size();
+      for (int t = 0; t < g.M; ++t) tl[slot].push_back(b);
+      e.set0 = nsets;
+      for (int s = 0; s < g.M; ++s) sl.push_back(b);
+      nsets += g.M;
+      e.wg0 = (int)wl.size();
+      e.nwg = nw[b];
+      for (int w = 0; w < nw[b]; ++w) wl.push_back(b);
+    }
+    nwg = (int)wl.size();
+    auto up = [&](const void* src, size_t bytes, void** dst) -> hipError_t {
+      hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+      if (e == hipSuccess && bytes) e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st);
+      return e;
+    };
+    void* p;
+    TB_TRY(up(h.data(), n * sizeof(BatchEntry), &p)); d_entries = (BatchEntry*)p;
+    for (int k = 0; k < 3; ++k) {
+      ntiles[k] = (int)tl[k].size();
+      TB_TRY(up(tl[k].data(), tl[k].size() * sizeof(int), &p)); d_tile_lat[k] = (int*)p;
+    }
+    TB_TRY(up(sl.data(), sl.size() * sizeof(int), &p)); d_set_lat = (int*)p;
+    TB_TRY(up(wl.data(), wl.size() * sizeof(int), &p)); d_wg_lat = (int*)p;
+    if (cap < n) {
+      if (d_ctrl) (void)hipFree(d_ctrl);
+      if (h_ctrl) (void)hipHostFree(h_ctrl);
+      d_ctrl = nullptr;
+      h_ctrl = nullptr;
+      TB_TRY(hipMalloc((void**)&d_ctrl, n * sizeof(Ctrl)));
+      TB_TRY(hipHostMalloc((void**)&h_ctrl, n * sizeof(Ctrl), hipHostMallocDefault));
+      cap = n;
+    }
+    TB_TRY(hipStreamSynchronize(st));   // the host tables are reused by the next build
+    return TL_OK;
+  }
+
+  // One outer iteration of every lattice in the batch.
+  tl_status enqueue_iteration(hipStream_t st) const {
+    static const int edges[3] = {16, 32, 64};
+    for (int k = 0; k < 3; ++k)
+      TB_TRY(launch_tile_batch(mixed, edges[k], d_entries, d_tile_lat[k], ntiles[k], st));
+    TB_TRY(launch_offdiag_batch(mixed, d_entries, d_set_lat, nsets, st));
+    TB_TRY(launch_blockinv_batch(d_entries, d_set_lat, nsets, st));
+    TB_TRY(launch_coarse_batch(d_entries, d_wg_lat, nwg, lds, st));
+    return TL_OK;
+  }
+
+  tl_status read_ctrl(hipStream_t st) {
+    const int n = (int)jobs.size();
+    TB_TRY(launch_gather_ctrl(d_entries, n, d_ctrl, st));
+    TB_TRY(hipMemcpyAsync(h_ctrl, d_ctrl, n * sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    TB_TRY(hipStreamSynchronize(st));
+    return TL_OK;
+  }
+};
+
+tl_status alloc_and_start(Job* j, hipStream_t st) {
+  if (!j->w) {
+    j->w = new (std::nothrow) Work();
+    if (!j->w) return TL_E_NOMEM;
+    j->own_work = true;
+    tl_status s = j->w->alloc(j->L->g, j->o.mixed, j->o.max_iters + 1);
+    if (s != TL_OK) return s;
+  }
+  return hip_status(launch_init_state(j->L->g, j->L->mask, j->L->ufix, (const double2*)j->u,
+                                      j->o.warm, j->w->u[0], j->w->u[1], j->w->d[0], j->w->d[1],
+                                      j->o.mixed, j->w->a, j->w->flags, j->w->ctrl, st));
 }
 
-tl_status start_job(Job* j, hipStream_t st) {
-  hipError_t e = launch_init_state(j->L->g, j->L->mask, j->L->ufix, (const double2*)j->u,
-                                   j->o.warm, j->w->u[0], j->w->u[1], j->w->d[0], j->w->d[1],
-                                   j->o.mixed, j->w->a, j->w->flags, j->w->ctrl, st);
-  if (e != hipSuccess) return hip_status(e);
-  j->k = 0;
-  j->live = true;
-  return TL_OK;
-}
-
-// Retire a job whose device flag is set: copy out u and certify it.
-void finish_job(Job* j, hipStream_t st) {
-  const Ctrl c = *j->w->ctrl_host;
-  j->live = false;
+// Retire a job whose control block says it stopped: copy out u and certify.
+void finish_job(Job* j, const Ctrl& c, hipStream_t st) {
   if (c.err) {
     j->status = TL_E_DEVICE;
   } else {
@@ -80,7 +251,6 @@ void finish_job(Job* j, hipStream_t st) {
         cs = certify(j->L, j->f, j->u, nullptr, out3, st);
       }
     }
-    j->info.status = (tl_status)c.status;
     j->info.iters = kf;
     j->info.rel_res_l1 = out3[0];
     j->info.rel_res_l2 = out3[1];
@@ -89,32 +259,15 @@ void finish_job(Job* j, hipStream_t st) {
     j->status = cs != TL_OK ? cs : (tl_status)c.status;
   }
   j->info.status = j->status;
-  j->finished = true;
   j->t_done = Clock::now();
 }
 
-// One round: enqueue up to `chunk` iterations of every live job, read the
-// flags, retire the finished jobs.  Returns a HIP failure, if any.
-tl_status run_round(std::vector<Job*>& live, int chunk, hipStream_t st) {
-  for (Job* j : live) {
-    for (int c = 0; c < chunk && j->k <= j->o.max_iters; ++c, ++j->k) {
-      tl_status s = enqueue_iteration(j->L, j->w, j->o, j->f, j->k, st);
-      if (s != TL_OK) return s;
-    }
-    hipError_t e = hipMemcpyAsync(j->w->ctrl_host, j->w->ctrl, sizeof(Ctrl),
-                                  hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return hip_status(e);
+void drop_work(Job* j) {
+  if (j->w && j->own_work) {
+    j->w->release();
+    delete j->w;
   }
-  hipError_t e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_status(e);
-  std::vector<Job*> keep;
-  for (Job* j : live) {
-    const Ctrl& c = *j->w->ctrl_host;
-    if (c.done || c.err || j->k > j->o.max_iters) finish_job(j, st);
-    else keep.push_back(j);
-  }
-  live.swap(keep);
-  return TL_OK;
+  j->w = nullptr;
 }
 
 }  // namespace
@@ -132,7 +285,6 @@ struct tl_server {
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Job*> queue;
-  std::vector<Job*> live;
   std::map<uint64_t, Job*> jobs;
   uint64_t next_ticket = 1;
   bool stopping = false;
@@ -143,15 +295,23 @@ namespace {
 
 size_t job_bytes(const Job* j) { return work_bytes(j->L->g, j->o.mixed, j->o.max_iters + 1); }
 
+// Requests are grouped by precision: one fused batch per precision.
 void server_loop(tl_server* S) {
   (void)hipSetDevice(S->device);
+  FusedBatch fb[2];
+  std::vector<Job*> live[2];
+  bool dirty[2] = {false, false};
+  const int chunk = 8;
   for (;;) {
     std::vector<Job*> admitted;
     {
       std::unique_lock<std::mutex> lock(S->mu);
-      S->cv.wait(lock, [&] { return S->stopping || !S->queue.empty() || !S->live.empty(); });
-      if (S->stopping && S->queue.empty() && S->live.empty()) return;
-      while (!S->queue.empty() && (int)S->live.size() + (int)admitted.size() < S->max_slots) {
+      S->cv.wait(lock, [&] {
+        return S->stopping || !S->queue.empty() || !live[0].empty() || !live[1].empty();
+      });
+      if (S->stopping && S->queue.empty() && live[0].empty() && live[1].empty()) break;
+      while (!S->queue.empty() &&
+             (int)(live[0].size() + live[1].size() + admitted.size()) < S->max_slots) {
         Job* j = S->queue.front();
         const size_t b = job_bytes(j);
         if (S->used + b > S->budget) break;
@@ -161,53 +321,56 @@ void server_loop(tl_server* S) {
       }
     }
     for (Job* j : admitted) {
-      j->w = new (std::nothrow) Work();
-      tl_status s = j->w ? j->w->alloc(j->L->g, j->o.mixed, j->o.max_iters + 1) : TL_E_NOMEM;
-      if (s == TL_OK) s = start_job(j, S->stream);
+      tl_status s = alloc_and_start(j, S->stream);
       if (s != TL_OK) {
+        drop_work(j);
+        std::lock_guard<std::mutex> lock(S->mu);
         j->status = s;
         j->info.status = s;
-        j->finished = true;
         j->t_done = Clock::now();
-        std::lock_guard<std::mutex> lock(S->mu);
-        if (j->w) { j->w->release(); delete j->w; j->w = nullptr; }
+        j->finished = true;
         S->used -= job_bytes(j);
         continue;
       }
-      std::lock_guard<std::mutex> lock(S->mu);
-      S->live.push_back(j);
+      const int m = j->o.mixed ? 1 : 0;
+      live[m].push_back(j);
+      dirty[m] = true;
     }
-    std::vector<Job*> live;
-    {
-      std::lock_guard<std::mutex> lock(S->mu);
-      live = S->live;
-    }
-    if (live.empty()) continue;
-    tl_status s = run_round(live, 8, S->stream);
-    std::lock_guard<std::mutex> lock(S->mu);
-    std::vector<Job*> still;
-    for (Job* j : S->live) {
-      if (s != TL_OK && !j->finished) {
-        j->status = s;
-        j->info.status = s;
-        j->finished = true;
-        j->t_done = Clock::now();
-        j->live = false;
+    for (int m = 0; m < 2; ++m) {
+      if (live[m].empty()) continue;
+      tl_status s = TL_OK;
+      if (dirty[m]) {
+        fb[m].jobs = live[m];
+        s = fb[m].build(S->stream);
+        dirty[m] = false;
       }
-      if (j->finished) {
-        if (j->w) {
-          (void)hipStreamSynchronize(S->stream);
-          j->w->release();
-          delete j->w;
-          j->w = nullptr;
+      for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb[m].enqueue_iteration(S->stream);
+      if (s == TL_OK) s = fb[m].read_ctrl(S->stream);
+      std::vector<Job*> still;
+      for (size_t b = 0; b < live[m].size(); ++b) {
+        Job* j = live[m][b];
+        if (s != TL_OK) {
+          j->status = s;
+          j->info.status = s;
+          j->t_done = Clock::now();
+        } else if (fb[m].h_ctrl[b].done || fb[m].h_ctrl[b].err) {
+          finish_job(j, fb[m].h_ctrl[b], S->stream);
+        } else {
+          still.push_back(j);
+          continue;
         }
+        (void)hipStreamSynchronize(S->stream);
+        drop_work(j);
+        std::lock_guard<std::mutex> lock(S->mu);
+        j->finished = true;      // published under the lock that tl_poll takes
         S->used -= job_bytes(j);
-      } else {
-        still.push_back(j);
+        dirty[m] = true;
       }
+      live[m].swap(still);
     }
-    S->live.swap(still);
   }
+  fb[0].release();
+  fb[1].release();
 }
 
 }  // namespace
@@ -220,77 +383,105 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
   if (n < 0 || (n > 0 && (!lats || !f_dev || !u_dev || !infos))) return TL_E_INVAL;
   for (int i = 0; i < n; ++i)
     if (!lats[i] || !f_dev[i] || !u_dev[i]) return TL_E_INVAL;
+  if (n == 0) return TL_OK;
   Opts o;
   resolve_opts(opts, &o);
   o.trace = nullptr;
-  hipStream_t st = (hipStream_t)hip_stream;
+  o.profile = 0;
+  hipStream_t user = (hipStream_t)hip_stream;
   std::vector<Job> jobs(n);
-  std::vector<Job*> live;
-  tl_status first = TL_OK;
-  // a lattice that appears once uses its cached work space; repeats get their own
   std::map<tl_lattice*, int> seen;
   for (int i = 0; i < n; ++i) seen[lats[i]]++;
   std::vector<std::unique_lock<std::mutex>> locks;
   for (auto& kv : seen) locks.emplace_back(kv.first->mu);
-  for (int i = 0; i < n; ++i) {
+  // a private stream, so that the chunk can be captured even when the
+  // caller passes the null stream; ordered after the caller's prior work
+  hipStream_t st;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return TL_E_DEVICE;
+  hipEvent_t ev_in, ev_out, e0, e1;
+  (void)hipEventCreate(&ev_in);
+  (void)hipEventCreate(&ev_out);
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)hipEventRecord(ev_in, user);
+  (void)hipStreamWaitEvent(st, ev_in, 0);
+  tl_status first = TL_OK;
+  FusedBatch fb;
+  for (int i = 0; i < n && first == TL_OK; ++i) {
     Job& j = jobs[i];
     j.L = lats[i];
     j.f = f_dev[i];
     j.u = u_dev[i];
     j.o = o;
     j.lock_lattice = false;
-    tl_status s = TL_OK;
-    if (seen[j.L] == 1) {
-      Work*& w = j.L->work[o.mixed ? 1 : 0];
-      if (!w || w->hist_cap < o.max_iters + 1) {
-        if (w) { w->release(); delete w; }
-        w = new (std::nothrow) Work();
-        s = w ? w->alloc(j.L->g, o.mixed, o.max_iters + 1) : TL_E_NOMEM;
-        if (s != TL_OK && w) { w->release(); delete w; w = nullptr; }
-      }
-      j.w = w;
-    } else {
-      j.w = new (std::nothrow) Work();
-      j.own_work = true;
-      s = j.w ? j.w->alloc(j.L->g, o.mixed, o.max_iters + 1) : TL_E_NOMEM;
+    if (seen[j.L] == 1) {   // a lattice that appears once uses its cached work space
+      tl_status err = TL_OK;
+      j.w = lattice_work(j.L, o.mixed, o.max_iters + 1, &err);
+      j.own_work = false;
+      if (!j.w) { first = err; break; }
     }
-    if (s == TL_OK) s = start_job(&j, st);
-    if (s != TL_OK) {
-      j.status = s;
-      j.info.status = s;
-      j.finished = true;
-      if (first == TL_OK) first = s;
-    } else {
-      live.push_back(&j);
-    }
+    first = alloc_and_start(&j, st);
+    if (first == TL_OK) fb.jobs.push_back(&j);
   }
-  hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
+  if (first == TL_OK) first = fb.build(st);
   (void)hipEventRecord(e0, st);
-  int chunk = 4;
-  while (!live.empty()) {
-    tl_status s = run_round(live, chunk, st);
-    if (s != TL_OK) {
-      for (Job* j : live) { j->status = s; j->info.status = s; j->finished = true; }
-      live.clear();
-      if (first == TL_OK) first = s;
+  if (first == TL_OK) {
+    // capture one chunk of iterations; replay until every lattice stopped
+    const int chunk = 8;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (use_graph) {
+      tl_status s = TL_OK;
+      for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb.enqueue_iteration(st);
+      const bool ended = hipStreamEndCapture(st, &graph) == hipSuccess;
+      use_graph = s == TL_OK && ended &&
+                  hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (!use_graph) (void)hipGetLastError();
     }
-    chunk = std::min(chunk * 2, 64);
+    int rounds = 0;
+    const int max_rounds = o.max_iters / chunk + 2;
+    for (;;) {
+      tl_status s = TL_OK;
+      if (use_graph) {
+        s = hipGraphLaunch(exec, st) == hipSuccess ? TL_OK : TL_E_DEVICE;
+      } else {
+        for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb.enqueue_iteration(st);
+      }
+      if (s == TL_OK) s = fb.read_ctrl(st);
+      if (s != TL_OK) { first = s; break; }
+      bool all = true;
+      for (int b = 0; b < n; ++b) all = all && (fb.h_ctrl[b].done || fb.h_ctrl[b].err);
+      if (all) break;
+      if (++rounds > max_rounds) { first = TL_E_DEVICE; break; }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
   }
   (void)hipEventRecord(e1, st);
   (void)hipEventSynchronize(e1);
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   for (int i = 0; i < n; ++i) {
     Job& j = jobs[i];
+    const bool ran = i < (int)fb.jobs.size() && fb.h_ctrl;
+    if (first == TL_OK && ran && (fb.h_ctrl[i].done || fb.h_ctrl[i].err)) {
+      finish_job(&j, fb.h_ctrl[i], st);
+      j.finished = true;
+    }
+    if (!j.finished) j.status = first != TL_OK ? first : TL_E_DEVICE;
+    j.info.status = j.status;
     j.info.ms = ms;
     infos[i] = j.info;
     if (j.status != TL_OK && first == TL_OK) first = j.status;
-    if (j.own_work && j.w) { j.w->release(); delete j.w; }
+    drop_work(&j);
   }
+  fb.release();
+  (void)hipEventRecord(ev_out, st);
+  (void)hipStreamWaitEvent(user, ev_out, 0);
+  (void)hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
+  for (hipEvent_t e : {ev_in, ev_out, e0, e1}) (void)hipEventDestroy(e);
   return first;
 }
 
@@ -301,7 +492,8 @@ tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, tl_server
   if (!S) return TL_E_NOMEM;
   S->budget = hbm_budget_bytes;
   S->max_slots = max_slots;
-  if (hipGetDevice(&S->device) != hipSuccess || hipStreamCreate(&S->stream) != hipSuccess) {
+  if (hipGetDevice(&S->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
     delete S;
     return TL_E_DEVICE;
   }
@@ -320,6 +512,7 @@ tl_status tl_submit(tl_server* S, tl_lattice* L, const double* f_dev, double* u_
   j->u = u_dev;
   resolve_opts(opts, &j->o);
   j->o.trace = nullptr;
+  j->o.profile = 0;
   if (job_bytes(j) > S->budget) { delete j; return TL_E_BUDGET; }
   j->t_submit = Clock::now();
   {

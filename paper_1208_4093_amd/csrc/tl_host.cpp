@@ -148,76 +148,83 @@ void resolve_opts(const tl_opts* o, Opts* r) {
   r->profile = o ? o->profile : 0;
 }
 
-// Enqueue outer iteration k of one solve.
-tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f, int k,
+// Arguments of one outer iteration's kernels for one solve (fixed for the
+// whole solve: the iteration counter and stop flag live in the control block).
+void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const double* f,
+                         TileArgs* ta, OffArgs* oa, BlockArgs* ba, CoarseArgs* ca) {
+  ta->u0 = w->u[0];
+  ta->u1 = w->u[1];
+  ta->d0 = w->d[0];
+  ta->d1 = w->d[1];
+  ta->a = w->a;
+  ta->f = (const double2*)f;
+  ta->krow = w->krow;
+  ta->force = w->force;
+  ta->nrm = w->nrm;
+  ta->ctrl = w->ctrl;
+  ta->inner_iters = o.inner;
+  ta->rhs_mode = L->ufix != nullptr;
+  oa->d0 = w->d[0];
+  oa->d1 = w->d[1];
+  oa->off = w->off;
+  oa->ctrl = w->ctrl;
+  ba->g1 = L->g1;
+  ba->krow = w->krow;
+  ba->bdiag = w->bdiag;
+  ba->binv = w->binv;
+  ba->ctrl = w->ctrl;
+  ca->g1 = L->g1;
+  ca->krow = w->krow;
+  ca->force = w->force;
+  ca->nrm = w->nrm;
+  ca->off = w->off;
+  ca->bdiag = w->bdiag;
+  ca->binv = w->binv;
+  ca->a = w->a;
+  ca->cr = w->cr;
+  ca->cu = w->cu;
+  ca->cw = w->cw;
+  ca->cz = w->cz;
+  ca->cq = w->cq;
+  ca->cs = w->cs;
+  ca->cp = w->cp;
+  ca->cn = w->cn;
+  ca->pub0 = w->pub0;
+  ca->pub1 = w->pub1;
+  ca->red = w->red;
+  ca->flags = w->flags;
+  ca->hist = (o.trace && o.trace->residual_history) ? o.trace->residual_history : w->hist;
+  ca->tr_kdiag = o.trace ? o.trace->kdiag : nullptr;
+  ca->tr_koff = o.trace ? o.trace->koff : nullptr;
+  ca->tr_force = o.trace ? o.trace->force : nullptr;
+  ca->tr_coef = o.trace ? o.trace->coef : nullptr;
+  ca->ctrl = w->ctrl;
+  ca->max_iters = o.max_iters;
+  ca->coarse_iters = o.coarse_iters;
+  ca->coarse_rtol = o.coarse_rtol;
+  ca->rtol = o.rtol;
+  ca->warm = env_int("TL_COARSE_WARM", 1);
+  ca->spin_limit = 1u << 22;
+  const CoarseShape cs = coarse_shape(L->g);
+  ca->nwg = cs.nwg;
+  ca->vec_lds = cs.vec_lds;
+  ca->blk_lds = cs.blk_lds;
+}
+
+// Enqueue one outer iteration of one solve (ev: optional 4 timing events).
+tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f,
                             hipStream_t st, hipEvent_t* ev) {
-  if (ev) TL_TRY(hipEventRecord(ev[0], st));
   TileArgs ta;
-  ta.u_in = w->u[k & 1];
-  ta.u_out = w->u[(k + 1) & 1];
-  ta.d_in = w->d[k & 1];
-  ta.d_out = w->d[(k + 1) & 1];
-  ta.a = w->a;
-  ta.f = (const double2*)f;
-  ta.krow = w->krow;
-  ta.force = w->force;
-  ta.nrm = w->nrm;
-  ta.ctrl = w->ctrl;
-  ta.inner_iters = o.inner;
-  ta.rhs_mode = L->ufix != nullptr;
+  OffArgs oa;
+  BlockArgs ba;
+  CoarseArgs ca;
+  make_iteration_args(L, w, o, f, &ta, &oa, &ba, &ca);
+  if (ev) TL_TRY(hipEventRecord(ev[0], st));
   TL_TRY(launch_tile(o.mixed, L->g, L->ea, L->mask, ta, st));
   if (ev) TL_TRY(hipEventRecord(ev[1], st));
-  OffArgs oa;
-  oa.d = w->d[(k + 1) & 1];
-  oa.off = w->off;
-  oa.ctrl = w->ctrl;
   TL_TRY(launch_offdiag(o.mixed, L->g, L->ea, L->mask, oa, st));
-  BlockArgs ba;
-  ba.g1 = L->g1;
-  ba.krow = w->krow;
-  ba.bdiag = w->bdiag;
-  ba.binv = w->binv;
-  ba.ctrl = w->ctrl;
   TL_TRY(launch_blockinv(L->g, ba, st));
   if (ev) TL_TRY(hipEventRecord(ev[2], st));
-  CoarseArgs ca;
-  ca.g1 = L->g1;
-  ca.krow = w->krow;
-  ca.force = w->force;
-  ca.nrm = w->nrm;
-  ca.off = w->off;
-  ca.bdiag = w->bdiag;
-  ca.binv = w->binv;
-  ca.a = w->a;
-  ca.cr = w->cr;
-  ca.cu = w->cu;
-  ca.cw = w->cw;
-  ca.cz = w->cz;
-  ca.cq = w->cq;
-  ca.cs = w->cs;
-  ca.cp = w->cp;
-  ca.cn = w->cn;
-  ca.pub0 = w->pub0;
-  ca.pub1 = w->pub1;
-  ca.red = w->red;
-  ca.flags = w->flags;
-  ca.hist = (o.trace && o.trace->residual_history) ? o.trace->residual_history : w->hist;
-  ca.tr_kdiag = o.trace ? o.trace->kdiag : nullptr;
-  ca.tr_koff = o.trace ? o.trace->koff : nullptr;
-  ca.tr_force = o.trace ? o.trace->force : nullptr;
-  ca.tr_coef = o.trace ? o.trace->coef : nullptr;
-  ca.ctrl = w->ctrl;
-  ca.iter = k;
-  ca.max_iters = o.max_iters;
-  ca.coarse_iters = o.coarse_iters;
-  ca.coarse_rtol = o.coarse_rtol;
-  ca.rtol = o.rtol;
-  const CoarseShape cs = coarse_shape(L->g);
-  ca.nwg = cs.nwg;
-  ca.vec_lds = cs.vec_lds;
-  ca.blk_lds = cs.blk_lds;
-  ca.warm = env_int("TL_COARSE_WARM", 1);
-  ca.spin_limit = 1u << 22;
   TL_TRY(launch_coarse(L->g, ca, st));
   if (ev) TL_TRY(hipEventRecord(ev[3], st));
   return TL_OK;
@@ -258,7 +265,7 @@ tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, doub
       }
     }
     for (int c = 0; c < chunk && k <= o.max_iters; ++c, ++k) {
-      st_run = enqueue_iteration(L, w, o, f, k, st, o.profile ? &w->events[4 * c] : nullptr);
+      st_run = enqueue_iteration(L, w, o, f, st, o.profile ? &w->events[4 * c] : nullptr);
       if (st_run != TL_OK) break;
     }
     if (st_run != TL_OK) break;

@@ -43,7 +43,8 @@ struct Geo {
 
 // Device-side control block of one solve.
 struct Ctrl {
-  int done;          // 0 running, else 1 + status code offset (see host)
+  int k;             // current outer iteration (advanced by the upper-level kernel)
+  int done;          // 0 running, 1 finished
   int status;        // tl_status of the finished solve
   int iters;         // outer iteration at which the solve finished
   int err;           // device-side abort (barrier time-out)
@@ -58,10 +59,10 @@ template <> struct V2<float> { using type = float2; };
 template <> struct V2<double> { using type = double2; };
 
 struct TileArgs {
-  const double2* u_in;
-  double2* u_out;
-  const void* d_in;      // T2 padded
-  void* d_out;           // T2 padded
+  double2* u0;           // padded displacements, ping (iteration k reads u[k & 1])
+  double2* u1;           // pong
+  void* d0;              // T2 padded relaxation increments, ping
+  void* d1;              // pong
   const double* a;       // [M][9] coefficients of the previous upper-level solve
   const double2* f;      // [ny][nx] loads (unpadded, caller's buffer)
   double* krow;          // [M][27]
@@ -99,7 +100,6 @@ struct CoarseArgs {
   double* tr_force;
   double* tr_coef;
   Ctrl* ctrl;
-  int iter;              // outer iteration index
   int max_iters;
   int coarse_iters;
   double coarse_rtol;
@@ -112,7 +112,8 @@ struct CoarseArgs {
 };
 
 struct OffArgs {
-  const void* d;         // T2 padded relaxation increments of this iteration
+  const void* d0;        // T2 padded relaxation increments (iteration k writes d[(k+1) & 1])
+  const void* d1;
   double* off;           // [M][6][81]
   const Ctrl* ctrl;
 };
@@ -125,6 +126,21 @@ struct BlockArgs {
   const Ctrl* ctrl;
 };
 
+// One lattice of a fused (batched) launch: its geometry, arguments of every
+// kernel, and its offsets in the launch-wide tile, set and workgroup ranges.
+struct BatchEntry {
+  Geo g;
+  const float* ea;
+  const uint8_t* mask;
+  TileArgs ta;
+  OffArgs oa;
+  BlockArgs ba;
+  CoarseArgs ca;
+  int tile0;             // first tile in its set-edge group's tile launch
+  int set0;              // first set in the launch-wide set range
+  int wg0, nwg;          // upper-level workgroups
+};
+
 // Launchers (tl_kernels.hip).  All are asynchronous on `stream`.
 hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
                        const TileArgs& a, hipStream_t stream);
@@ -133,6 +149,17 @@ hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8
 hipError_t launch_blockinv(const Geo& g, const BlockArgs& a, hipStream_t stream);
 hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream);
 size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds);
+// Fused launches over a batch (entries and lookup tables in device memory).
+hipError_t launch_tile_batch(bool mixed, int E, const BatchEntry* B, const int* tile_lat,
+                             int ntiles, hipStream_t stream);
+hipError_t launch_offdiag_batch(bool mixed, const BatchEntry* B, const int* set_lat, int nsets,
+                                hipStream_t stream);
+hipError_t launch_blockinv_batch(const BatchEntry* B, const int* set_lat, int nsets,
+                                 hipStream_t stream);
+hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, int nwg, size_t lds,
+                               hipStream_t stream);
+int coarse_batch_capacity(size_t lds);   // co-resident workgroups of the fused upper-level kernel
+hipError_t launch_gather_ctrl(const BatchEntry* B, int n, Ctrl* out, hipStream_t stream);
 hipError_t launch_group1(const Geo& g, const float* ea, const uint8_t* mask, double* g1,
                          hipStream_t stream);
 hipError_t launch_init_state(const Geo& g, const uint8_t* mask, const double2* u_fixed,

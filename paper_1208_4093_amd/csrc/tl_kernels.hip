@@ -110,8 +110,9 @@ template <> __device__ __forceinline__ double2 mk2<double>(double x, double y) {
 // Tile kernel: update + residual + local relaxation + set's upper-level rows.
 // ---------------------------------------------------------------------------
 template <typename T, int E, int NT>
-__global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea,
-                                             const uint8_t* __restrict__ mask, TileArgs A) {
+__device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict__ ea,
+                                          const uint8_t* __restrict__ mask, const TileArgs& A,
+                                          const int tile) {
   using T2 = typename V2<T>::type;
   constexpr int NPT = E * E / NT;
   constexpr int W = E + 2;
@@ -125,7 +126,11 @@ __global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea
   T2* sp = reinterpret_cast<T2*>(su);
 
   if (A.ctrl->done) return;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int kit = A.ctrl->k;
+  const double2* u_in = (kit & 1) ? A.u1 : A.u0;
+  double2* u_out = (kit & 1) ? A.u0 : A.u1;
+  const void* d_in_v = (kit & 1) ? A.d1 : A.d0;
+  void* d_out_v = (kit & 1) ? A.d0 : A.d1;
   const int I = tile % g.mx, J = tile / g.mx;
   const int i0 = I * E, j0 = J * E;
   const int tw = min(E, g.nx - i0), th = min(E, g.ny - j0);
@@ -142,28 +147,48 @@ __global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea
   __syncthreads();
 
   // 1. u_new = u_old + sum_m a_m u_hat_m (Eq. 3) on the tile and its halo.
+  //    All loads of a thread's region nodes are issued before any is used,
+  //    so the phase costs one memory latency instead of one per node.
   {
-    const T2* din = reinterpret_cast<const T2*>(A.d_in);
+    constexpr int RIT = ((E + 2) * (E + 2) + NT - 1) / NT;
+    const T2* din = reinterpret_cast<const T2*>(d_in_v);
     const int rw = tw + 2, rn = (tw + 2) * (th + 2);
-    for (int idx = t; idx < rn; idx += NT) {
+    double2 ul[RIT];
+    T2 dl[RIT];
+    uint8_t ml[RIT];
+#pragma unroll
+    for (int k = 0; k < RIT; ++k) {
+      const int idx = t + k * NT;
+      ml[k] = 1;
+      ul[k] = make_double2(0.0, 0.0);
+      dl[k] = mk2<T>((T)0, (T)0);
+      if (idx < rn) {
+        const size_t p = pidx(g, i0 - 1 + idx % rw, j0 - 1 + idx / rw);
+        ul[k] = u_in[p];
+        ml[k] = mask[p];
+        dl[k] = din[p];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RIT; ++k) {
+      const int idx = t + k * NT;
+      if (idx >= rn) continue;
       const int ri = idx % rw, rj = idx / rw;
       const int gi = i0 - 1 + ri, gj = j0 - 1 + rj;
-      const size_t p = pidx(g, gi, gj);
-      double2 u = A.u_in[p];
-      if (!mask[p]) {
+      double2 u = ul[k];
+      if (!ml[k]) {
         const int dI = ri == 0 ? -1 : (ri == tw + 1 ? 1 : 0);
         const int dJ = rj == 0 ? -1 : (rj == th + 1 ? 1 : 0);
         const int oi0 = (I + dI) * E, oj0 = (J + dJ) * E;
         double xi, eta;
         set_coords(gi, gj, oi0, oj0, min(E, g.nx - oi0), min(E, g.ny - oj0), inv_hs, xi, eta);
         const double* c = sa[(dJ + 1) * 3 + (dI + 1)];
-        const T2 dl = din[p];
         const double w = c[6] + c[7] * xi + c[8] * eta;
-        u.x += c[0] + c[2] * xi + c[3] * eta + w * (double)dl.x;
-        u.y += c[1] + c[4] * xi + c[5] * eta + w * (double)dl.y;
+        u.x += c[0] + c[2] * xi + c[3] * eta + w * (double)dl[k].x;
+        u.y += c[1] + c[4] * xi + c[5] * eta + w * (double)dl[k].y;
       }
       su[rj * W + ri] = u;
-      if (ri >= 1 && ri <= tw && rj >= 1 && rj <= th) A.u_out[p] = u;
+      if (ri >= 1 && ri <= tw && rj >= 1 && rj <= th) u_out[pidx(g, gi, gj)] = u;
     }
   }
   __syncthreads();
@@ -177,26 +202,35 @@ __global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea
 #pragma unroll
   for (int v = 0; v < 10; ++v) part[v] = 0.0;
   double rmax = 0.0;
+  double2 fl[NPT];
+  // all of the thread's loads first (one memory latency), then the arithmetic
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = t + k * NT, li = n % E, lj = n / E;
-    const bool inside = li < tw && lj < th;
     act[k] = false;
-    r[k] = make_double2(0.0, 0.0);
+    fl[k] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int b = 0; b < 6; ++b) kk[k][b] = 0.f;
+    if (li < tw && lj < th) {
+      const size_t p = pidx(g, i0 + li, j0 + lj);
+      act[k] = mask[p] == 0;
+      kk[k][0] = ea[p];
+      kk[k][1] = ea[plane + p];
+      kk[k][2] = ea[2 * plane + p];
+      kk[k][3] = ea[p - 1];
+      kk[k][4] = ea[plane + p - g.pitch];
+      kk[k][5] = ea[2 * plane + p - g.pitch + 1];
+      fl[k] = A.f[(size_t)(j0 + lj) * g.nx + (i0 + li)];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int n = t + k * NT, li = n % E, lj = n / E;
+    r[k] = make_double2(0.0, 0.0);
     dxx[k] = dxy[k] = dyy[k] = ixx[k] = ixy[k] = iyy[k] = (T)0;
-    if (!inside) continue;
+    if (!act[k]) continue;
     const int gi = i0 + li, gj = j0 + lj;
     const size_t p = pidx(g, gi, gj);
-    if (mask[p]) continue;
-    act[k] = true;
-    kk[k][0] = ea[p];
-    kk[k][1] = ea[plane + p];
-    kk[k][2] = ea[2 * plane + p];
-    kk[k][3] = ea[p - 1];
-    kk[k][4] = ea[plane + p - g.pitch];
-    kk[k][5] = ea[2 * plane + p - g.pitch + 1];
     const int c = (lj + 1) * W + (li + 1);
     const double2 ua = su[c];
     double kx = 0.0, ky = 0.0;
@@ -211,7 +245,7 @@ __global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea
     rod(kk[k][3], 1.0, 0.0, su[c - 1]);
     rod(kk[k][4], 0.5, kS3, su[c - W]);
     rod(kk[k][5], -0.5, kS3, su[c - W + 1]);
-    double2 fv = A.f[(size_t)gj * g.nx + gi];
+    double2 fv = fl[k];
     const double rx = fv.x - kx, ry = fv.y - ky;
     if (A.rhs_mode) {
       // right-hand side of the constrained system: f - K_fc u_c, i.e. the
@@ -341,7 +375,7 @@ __global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea
 
   // 4. store the relaxation increment (mode 7 as stored, scaled in float32)
   {
-    T2* dout = reinterpret_cast<T2*>(A.d_out);
+    T2* dout = reinterpret_cast<T2*>(d_out_v);
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
       const int n = t + k * NT, li = n % E, lj = n / E;
@@ -424,6 +458,22 @@ __global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea
   }
 }
 
+template <typename T, int E, int NT>
+__global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea,
+                                             const uint8_t* __restrict__ mask, TileArgs A) {
+  tile_body<T, E, NT>(g, ea, mask, A, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Fused launch over the tiles of several lattices with the same set edge:
+// tile_lat maps a launch-wide tile index to its lattice entry.
+template <typename T, int E, int NT>
+__global__ __launch_bounds__(NT) void k_tile_batch(const BatchEntry* __restrict__ B,
+                                                   const int* __restrict__ tile_lat) {
+  const int gt = xcd_remap(blockIdx.x, gridDim.x);
+  const BatchEntry& e = B[tile_lat[gt]];
+  tile_body<T, E, NT>(e.g, e.ea, e.mask, e.ta, gt - e.tile0);
+}
+
 namespace {
 
 __device__ __forceinline__ int lpk(int i, int j) { return i * (i + 1) / 2 + j; }
@@ -487,19 +537,20 @@ __device__ void block_pinv(const double* B, double* Binv) {
 // boundary cuts: K[Im][Jl] = -sum_rods k (n . u_hat_m^I(a)) (n . u_hat_l^J(c)).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_offdiag(Geo g, const float* __restrict__ ea,
-                                                 const uint8_t* __restrict__ mask, OffArgs A) {
+__device__ __forceinline__ void offdiag_body(const Geo& g, const float* __restrict__ ea,
+                                             const uint8_t* __restrict__ mask, const OffArgs& A,
+                                             const int s) {
   using T2 = typename V2<T>::type;
   constexpr int MAXB = 2 * 64;
   __shared__ double G[MAXB][Q];
   __shared__ double H[MAXB][Q];
   if (A.ctrl->done) return;
-  const int s = blockIdx.x, I = s % g.mx, J = s / g.mx;
+  const T2* d = reinterpret_cast<const T2*>((A.ctrl->k & 1) ? A.d0 : A.d1);
+  const int I = s % g.mx, J = s / g.mx;
   const int E = g.E;
   const int i0 = I * E, j0 = J * E, tw = min(E, g.nx - i0), th = min(E, g.ny - j0);
   const size_t plane = (size_t)(g.ny + 2) * g.pitch;
   const double inv_hs = 2.0 / E;
-  const T2* d = reinterpret_cast<const T2*>(A.d);
   const int t = threadIdx.x;
 
   for (int dir = 0; dir < 3; ++dir) {
@@ -550,15 +601,29 @@ __global__ __launch_bounds__(256) void k_offdiag(Geo g, const float* __restrict_
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_offdiag(Geo g, const float* __restrict__ ea,
+                                                 const uint8_t* __restrict__ mask, OffArgs A) {
+  offdiag_body<T>(g, ea, mask, A, blockIdx.x);
+}
+
+// Fused launch over the sets of several lattices; set_lat maps a launch-wide
+// set index to its lattice entry.
+template <typename T>
+__global__ __launch_bounds__(256) void k_offdiag_batch(const BatchEntry* __restrict__ B,
+                                                       const int* __restrict__ set_lat) {
+  const BatchEntry& e = B[set_lat[blockIdx.x]];
+  offdiag_body<T>(e.g, e.ea, e.mask, e.oa, blockIdx.x - e.set0);
+}
+
 // ---------------------------------------------------------------------------
 // Each set's diagonal upper-level block: the constant translation/gradient
 // part plus the rows of the relaxation modes from the tile kernel (Eq. 6),
 // and its pseudo-inverse for the block-Jacobi preconditioner.  One thread
 // per set.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_blockinv(Geo g, BlockArgs A) {
+__device__ __forceinline__ void blockinv_body(const Geo& g, const BlockArgs& A, const int s) {
   if (A.ctrl->done) return;
-  const int s = blockIdx.x * 64 + threadIdx.x;
   if (s >= g.M) return;
   double B[Q * Q];
   const double* g1 = A.g1 + (size_t)s * 36;
@@ -575,6 +640,19 @@ __global__ __launch_bounds__(64) void k_blockinv(Geo g, BlockArgs A) {
   block_pinv(B, Bi);
   double* bi = A.binv + (size_t)s * Q * Q;
   for (int v = 0; v < Q * Q; ++v) bi[v] = Bi[v];
+}
+
+__global__ __launch_bounds__(64) void k_blockinv(Geo g, BlockArgs A) {
+  blockinv_body(g, A, blockIdx.x * 64 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(64) void k_blockinv_batch(const BatchEntry* __restrict__ B,
+                                                       const int* __restrict__ set_lat,
+                                                       int nsets) {
+  const int gs = blockIdx.x * 64 + threadIdx.x;
+  if (gs >= nsets) return;
+  const BatchEntry& e = B[set_lat[gs]];
+  blockinv_body(e.g, e.ba, gs - e.set0);
 }
 
 // ---------------------------------------------------------------------------
@@ -617,8 +695,8 @@ __device__ __forceinline__ double pub_load(const double* p) {
 // memory round trip is made.
 template <int NV>
 __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* flags,
-                                  unsigned gen, int slot, Ctrl* c, int nwg, unsigned spin,
-                                  double* sslot, double* sv) {
+                                  unsigned gen, int slot, Ctrl* c, int wid, int nwg,
+                                  unsigned spin, double* sslot, double* sv) {
   __shared__ int ok;
   static_assert(NV <= REDW, "too many values for one grid sum");
   __builtin_amdgcn_s_waitcnt(0);   // every wave's published stores have completed
@@ -627,7 +705,7 @@ __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* 
     const double bs = block_sum<COARSE_NT / 64>(v[k], sslot);
     if (threadIdx.x == 0) {
       if (nwg == 1) sv[k] = bs;
-      else pub_store(&red[((size_t)slot * COARSE_MAX_WG + blockIdx.x) * REDW + k], bs);
+      else pub_store(&red[((size_t)slot * COARSE_MAX_WG + wid) * REDW + k], bs);
     }
     __syncthreads();
   }
@@ -636,7 +714,7 @@ __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* 
     int good = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     if (threadIdx.x == 0 && good) {
       __builtin_amdgcn_s_waitcnt(0);
-      __hip_atomic_store(&flags[blockIdx.x], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&flags[wid], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     unsigned n = 0;
     while (good) {
@@ -726,13 +804,14 @@ size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds) {
 // recurrences): per iteration one grid sum carries both dot products and
 // orders the publication of m = B^+ w, whose neighbour values the product
 // n = K_a m needs, so one grid synchronisation per iteration.
-__global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
+__device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, const int w,
+                                            const int nwg) {
   extern __shared__ double lds[];
   __shared__ double sslot[COARSE_NT / 64];
   __shared__ double sv[REDW];
   Ctrl* ctrl = A.ctrl;
   if (ctrl->done) return;
-  const int w = blockIdx.x, nwg = gridDim.x, t = threadIdx.x;
+  const int t = threadIdx.x;
   const int M = g.M;
   const int spw = (M + nwg - 1) / nwg;
   const int s0 = min(M, w * spw), s1 = min(M, s0 + spw), ns = s1 - s0;
@@ -741,6 +820,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   const int nrow = ns * Q;
   const unsigned spin = A.spin_limit;
   const unsigned base = ctrl->bar_gen;
+  const int iter = ctrl->k;
   unsigned nsync = 0;
   int slot = 0;
   const int wmax = min(M, spw + 2 * g.mx + 2);
@@ -788,7 +868,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   //     theta = (a_prev . P) / (a_prev . y).  One grid sum carries theta's
   //     two dot products, the stop test's four norm sums, and orders the
   //     publication of B^+ P and B^+ y.
-  const bool warm = A.warm && A.iter > 0;
+  const bool warm = A.warm && iter > 0;
   for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = warm ? A.a[(size_t)w0 * Q + e] : 0.0;
   __syncthreads();
   double red6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -821,7 +901,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
     pub_store(&A.pub1[r0 + e], v);    // B^+ y
     vq[e] = v;
   }
-  if (!grid_publish_wait<6>(red6, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot, sv))
+  if (!grid_publish_wait<6>(red6, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
     return;
   grid_collect<6>(A.red, slot, nwg, sv);
   slot ^= 1;
@@ -835,14 +915,14 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
     int status = -100;   // continue
     if (!isfinite(red6[0]) || !isfinite(red6[1]) || !isfinite(red6[2]) || !isfinite(red6[3])) status = -6;
     else if (R <= A.rtol) status = 0;
-    else if (A.iter >= A.max_iters) status = -3;
+    else if (iter >= A.max_iters) status = -3;
     if (w == 0 && t == 0) {
-      if (A.hist) A.hist[A.iter] = R;
+      if (A.hist) A.hist[iter] = R;
       ctrl->r1 = R1;
       ctrl->r2 = R2;
       if (status != -100) {
         ctrl->status = status;
-        ctrl->iters = A.iter;
+        ctrl->iters = iter;
         ctrl->done = 1;
         ctrl->bar_gen = base + nsync;
       }
@@ -911,7 +991,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
         if (nwg == 1) lw1[t] = mv;
         else pub_store(&mpub[r0 + t], mv);
       }
-      if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot, sv))
+      if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
         return;
       grid_collect<2>(A.red, slot, nwg, sv);
       if (nwg > 1)
@@ -970,7 +1050,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
       if (nwg == 1) lw1[e] = mv;            // one workgroup: the window is its own sets
       else pub_store(&mpub[r0 + e], mv);
     }
-    if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, nwg, spin, sslot, sv))
+    if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
       return;
     // one round trip: the partial sums and the neighbours' m together
     grid_collect<2>(A.red, slot, nwg, sv);
@@ -1014,6 +1094,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   if (w == 0 && t == 0) {
     ctrl->coarse_iters += it;
     ctrl->bar_gen = base + nsync;
+    ctrl->k = iter + 1;      // every workgroup read k at its start (before the first grid sum)
   }
   // diagnostics: the upper-level system just solved
   if (A.tr_kdiag)
@@ -1024,6 +1105,18 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
     for (size_t e = (size_t)s0 * Q + t; e < (size_t)s1 * Q; e += COARSE_NT) A.tr_force[e] = A.force[e];
   if (A.tr_coef)
     for (int e = t; e < nrow; e += COARSE_NT) A.tr_coef[r0 + e] = A.a[r0 + e];
+}
+
+__global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
+  coarse_body(g, A, blockIdx.x, gridDim.x);
+}
+
+// Fused launch: lattice b owns workgroups [wg0, wg0 + nwg) and runs its own
+// grid sums among them; the launch is sized to be co-resident.
+__global__ __launch_bounds__(COARSE_NT) void k_coarse_batch(const BatchEntry* __restrict__ B,
+                                                            const int* __restrict__ wg_lat) {
+  const BatchEntry& e = B[wg_lat[blockIdx.x]];
+  coarse_body(e.g, e.ca, blockIdx.x - e.wg0, e.nwg);
 }
 
 // ---------------------------------------------------------------------------
@@ -1134,7 +1227,7 @@ __global__ void k_init_state(Geo g, const uint8_t* __restrict__ mask, const doub
   for (size_t e = tid; e < (size_t)g.M * Q; e += nt) a[e] = 0.0;
   for (size_t e = tid; e < (size_t)COARSE_MAX_WG; e += nt) flags[e] = 0u;
   if (tid == 0) {
-    ctrl->done = 0; ctrl->status = 0; ctrl->iters = 0; ctrl->err = 0;
+    ctrl->k = 0; ctrl->done = 0; ctrl->status = 0; ctrl->iters = 0; ctrl->err = 0;
     ctrl->coarse_iters = 0; ctrl->r1 = 0.0; ctrl->r2 = 0.0;
     ctrl->bar_count = 0u; ctrl->bar_gen = 0u;
   }
@@ -1267,7 +1360,7 @@ static int tile_threads(int E, bool mixed) {
   const char* v = getenv("TL_TILE_THREADS");
   const int env = v && *v ? atoi(v) : 0;
   if (E == 16) return 256;
-  if (E == 32) return env == 256 || env == 512 ? env : 256;
+  if (E == 32) return env == 256 || env == 512 || env == 1024 ? env : 256;
   return env == 512 || env == 1024 ? env : (mixed ? 512 : 1024);
 }
 
@@ -1279,7 +1372,8 @@ hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t*
 #define TL_TILE_ALL(T)                                   \
   if (g.E == 16) TL_TILE(T, 16, 256);                    \
   else if (g.E == 32 && nt == 256) TL_TILE(T, 32, 256);  \
-  else if (g.E == 32) TL_TILE(T, 32, 512);               \
+  else if (g.E == 32 && nt == 512) TL_TILE(T, 32, 512);  \
+  else if (g.E == 32) TL_TILE(T, 32, 1024);              \
   else if (g.E == 64 && nt == 512) TL_TILE(T, 64, 512);  \
   else if (g.E == 64) TL_TILE(T, 64, 1024);              \
   else return hipErrorInvalidValue;
@@ -1290,6 +1384,86 @@ hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t*
   }
 #undef TL_TILE_ALL
 #undef TL_TILE
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_batch(bool mixed, int E, const BatchEntry* B, const int* tile_lat,
+                             int ntiles, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  const dim3 grid(ntiles);
+  const int nt = tile_threads(E, mixed);
+#define TL_TILEB(T, EE, NT) hipLaunchKernelGGL((k_tile_batch<T, EE, NT>), grid, dim3(NT), 0, stream, B, tile_lat)
+#define TL_TILEB_ALL(T)                                    \
+  if (E == 16) TL_TILEB(T, 16, 256);                       \
+  else if (E == 32 && nt == 256) TL_TILEB(T, 32, 256);     \
+  else if (E == 32 && nt == 512) TL_TILEB(T, 32, 512);     \
+  else if (E == 32) TL_TILEB(T, 32, 1024);                 \
+  else if (E == 64 && nt == 512) TL_TILEB(T, 64, 512);     \
+  else if (E == 64) TL_TILEB(T, 64, 1024);                 \
+  else return hipErrorInvalidValue;
+  if (mixed) {
+    TL_TILEB_ALL(float)
+  } else {
+    TL_TILEB_ALL(double)
+  }
+#undef TL_TILEB_ALL
+#undef TL_TILEB
+  return hipGetLastError();
+}
+
+hipError_t launch_offdiag_batch(bool mixed, const BatchEntry* B, const int* set_lat, int nsets,
+                                hipStream_t stream) {
+  if (nsets <= 0) return hipSuccess;
+  if (mixed) hipLaunchKernelGGL(k_offdiag_batch<float>, dim3(nsets), dim3(256), 0, stream, B, set_lat);
+  else hipLaunchKernelGGL(k_offdiag_batch<double>, dim3(nsets), dim3(256), 0, stream, B, set_lat);
+  return hipGetLastError();
+}
+
+hipError_t launch_blockinv_batch(const BatchEntry* B, const int* set_lat, int nsets,
+                                 hipStream_t stream) {
+  if (nsets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_blockinv_batch, dim3((nsets + 63) / 64), dim3(64), 0, stream, B, set_lat, nsets);
+  return hipGetLastError();
+}
+
+int coarse_batch_capacity(size_t lds) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute((const void*)k_coarse_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024 - 1024) != hipSuccess)
+      return 0;
+    attr_set = true;
+  }
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_coarse_batch, COARSE_NT,
+                                                   lds) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, int nwg, size_t lds,
+                               hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+  if (coarse_batch_capacity(lds) < nwg) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_coarse_batch, dim3(nwg), dim3(COARSE_NT), lds, stream, B, wg_lat);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_ctrl(const BatchEntry* __restrict__ B, int n, Ctrl* out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n) out[b] = *B[b].ca.ctrl;
+}
+
+hipError_t launch_gather_ctrl(const BatchEntry* B, int n, Ctrl* out, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_ctrl, dim3((n + 63) / 64), dim3(64), 0, stream, B, n, out);
   return hipGetLastError();
 }
 

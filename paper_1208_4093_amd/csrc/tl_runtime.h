@@ -77,8 +77,12 @@ struct CoarseShape {
 };
 CoarseShape coarse_shape(const Geo& g);
 void resolve_opts(const tl_opts* o, Opts* r);
-tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f, int k,
+void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const double* f,
+                         TileArgs* ta, OffArgs* oa, BlockArgs* ba, CoarseArgs* ca);
+tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f,
                             hipStream_t st, hipEvent_t* ev = nullptr);
+// The lattice's cached work space for one precision (caller holds L->mu).
+Work* lattice_work(tl_lattice* L, bool mixed, int hist_cap, tl_status* err);
 tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, double* u,
                     tl_info* info, hipStream_t st);
 tl_status certify(const tl_lattice* L, const double* f, const double* u, double* r,
