@@ -55,7 +55,9 @@ typedef enum {
     TL_E_NOMEM = -2,       /* device allocation failed                          */
     TL_E_NOCONV = -3,      /* max_iters reached before the tolerance            */
     TL_E_DEVICE = -4,      /* HIP runtime error or a device-side abort          */
-    TL_E_BUDGET = -5,      /* request can never fit the server's HBM budget     */
+    TL_E_BUDGET = -5,      /* request can never fit the server's HBM budget, or a
+                              lattice's upper-level workgroups cannot all be
+                              co-resident on the device                         */
     TL_E_NONFINITE = -6    /* non-finite input or iterate                        */
 } tl_status;
 
@@ -139,10 +141,17 @@ tl_status tl_lattice_get_facts(const tl_lattice* lat, tl_lattice_facts* out);
 tl_status tl_solve(tl_lattice* lat, const double* f_dev, double* u_dev,
                    const tl_opts* opts, tl_info* info, void* hip_stream);
 
-/* Solve n independent lattices in fused launches: one tile kernel over the
- * sets of all lattices, one upper-level kernel over all lattices.  infos[k]
- * receives lattice k's result; the return value is TL_OK when every lattice
- * converged, else the first failing status. */
+/* Solve n independent lattices in fused launches: per outer iteration one
+ * tile launch per set edge over the sets of all lattices, one boundary-block
+ * and one block-inverse launch over all sets, and one persistent upper-level
+ * launch in which every lattice owns its own range of workgroups; chunks of
+ * iterations are captured once in a hipGraph and replayed.  The lattices are
+ * taken in order into groups whose upper-level workgroups fit co-resident on
+ * the device; groups run one after another.  Each lattice's result is bit for
+ * bit the one tl_solve gives it alone (its kernels, set edge and reduction
+ * orders depend on that lattice only).  infos[k] receives lattice k's result
+ * (ms = device time of the whole call); the return value is TL_OK when every
+ * lattice converged, else the first failing status. */
 tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const* f_dev,
                          double* const* u_dev, const tl_opts* opts, tl_info* infos,
                          void* hip_stream);
@@ -153,10 +162,14 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
 tl_status tl_residual(tl_lattice* lat, const double* f_dev, const double* u_dev,
                       double* r_dev, double out[3], void* hip_stream);
 
-/* Continuous-batching server.  Requests are admitted while the device state
- * of all admitted requests fits hbm_budget_bytes and fewer than max_slots are
- * admitted; a background worker advances all admitted requests together, one
- * fused outer iteration at a time, and retires each as it converges. */
+/* Continuous-batching server.  Requests are admitted in arrival order while
+ * the device state of all admitted requests fits hbm_budget_bytes, fewer than
+ * max_slots are admitted, and the upper-level workgroups of the admitted
+ * requests of one precision fit co-resident; a background worker advances all
+ * admitted requests of a precision together in fused launches, eight outer
+ * iterations at a time, retires each as it converges and admits waiting
+ * requests at once.  Results are bit for bit those of tl_solve alone.
+ * tl_submit returns TL_E_BUDGET for a request that could never be admitted. */
 tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, tl_server** out);
 tl_status tl_submit(tl_server* srv, tl_lattice* lat, const double* f_dev, double* u_dev,
                     const tl_opts* opts, uint64_t* ticket);

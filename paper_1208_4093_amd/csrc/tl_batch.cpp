@@ -63,6 +63,57 @@ struct Job {
   bool lock_lattice = true;  // false when the caller already holds the lattice lock
 };
 
+// Workgroup plan of a fused upper-level launch.  Each lattice gets the
+// workgroup count of its single-lattice shape, which depends on the lattice
+// alone, so its grid-sum order, and with it every rounding, is the same alone
+// and in any batch.  All workgroups of the launch must be co-resident (each
+// lattice's grid sums wait on its own workgroups), so the plan picks an LDS
+// size class (76 KB: two workgroups per CU; else 150 KB: one) that every
+// lattice's unstaged slice fits, checks the total against the co-resident
+// capacity at that class, and enables LDS staging per lattice where it still
+// fits the class.  Returns false when the lattices cannot all be co-resident.
+bool plan_coarse(const std::vector<const Geo*>& gs, std::vector<int>* nw_out,
+                 std::vector<CoarseShape>* shape_out, size_t* lds_out) {
+  const int n = (int)gs.size();
+  std::vector<CoarseShape> shape(n);
+  std::vector<int> nw(n);
+  long used = 0;
+  for (int b = 0; b < n; ++b) {
+    shape[b] = coarse_shape(*gs[b]);
+    nw[b] = shape[b].nwg;
+    used += nw[b];
+  }
+  static const size_t classes[2] = {76 * 1024, 150 * 1024};
+  for (size_t cap : classes) {
+    bool ok = true;
+    for (int b = 0; b < n && ok; ++b) ok = coarse_lds_bytes(*gs[b], nw[b], 0, 0) <= cap;
+    if (!ok || coarse_batch_capacity(cap) < used) continue;
+    size_t lds = 0;
+    for (int b = 0; b < n; ++b) {
+      const int vec = shape[b].vec_lds && coarse_lds_bytes(*gs[b], nw[b], 1, 0) <= cap;
+      const int blk = vec && shape[b].blk_lds && coarse_lds_bytes(*gs[b], nw[b], 1, 1) <= cap;
+      shape[b].vec_lds = vec;
+      shape[b].blk_lds = blk;
+      lds = std::max(lds, coarse_lds_bytes(*gs[b], nw[b], vec, blk));
+    }
+    *nw_out = nw;
+    *shape_out = shape;
+    *lds_out = lds;
+    return true;
+  }
+  return false;
+}
+
+// True when the jobs' upper-level workgroups can all be co-resident.
+bool coresident(const std::vector<Job*>& jobs) {
+  std::vector<const Geo*> gs;
+  for (Job* j : jobs) gs.push_back(&j->L->g);
+  std::vector<int> nw;
+  std::vector<CoarseShape> shape;
+  size_t lds = 0;
+  return plan_coarse(gs, &nw, &shape, &lds);
+}
+
 // Device tables of one fused batch.
 struct FusedBatch {
   std::vector<Job*> jobs;
@@ -108,49 +159,11 @@ struct FusedBatch {
     mixed = jobs[0]->o.mixed;
     h.assign(n, BatchEntry{});
     std::vector<int> tl[3], sl;
-    // upper-level workgroups: one each, then the rest of the co-resident
-    // capacity to the lattices with the most sets, within their own shape
-    std::vector<CoarseShape> shape(n);
-    std::vector<int> nw(n, 1);
-    for (int b = 0; b < n; ++b) shape[b] = coarse_shape(jobs[b]->L->g);
-    // co-resident workgroups at the LDS budget used below (80 KB: two per CU)
-    const int capacity = coarse_batch_capacity(80 * 1024);
-    if (capacity < n) return TL_E_DEVICE;
-    int used = n;
-    std::vector<int> order(n);
-    for (int b = 0; b < n; ++b) order[b] = b;
-    std::sort(order.begin(), order.end(),
-              [&](int x, int y) { return jobs[x]->L->g.M > jobs[y]->L->g.M; });
-    bool grew = true;
-    while (grew && used < capacity) {
-      grew = false;
-      for (int b : order) {
-        if (used >= capacity) break;
-        if (nw[b] < shape[b].nwg) { ++nw[b]; ++used; grew = true; }
-      }
-    }
-    // with fewer workgroups than the single-lattice shape, LDS staging may
-    // no longer fit: decide per lattice, then size the launch's LDS
-    size_t lds_need = 0;
-    for (int b = 0; b < n; ++b) {
-      const Geo& g = jobs[b]->L->g;
-      if (coarse_lds_bytes(g, nw[b], 0, 0) > 150 * 1024) return TL_E_INVAL;
-      const int vec = coarse_lds_bytes(g, nw[b], 1, 0) <= 80 * 1024;
-      const int blk = vec && coarse_lds_bytes(g, nw[b], 1, 1) <= 80 * 1024;
-      shape[b].vec_lds = vec;
-      shape[b].blk_lds = blk;
-      lds_need = std::max(lds_need, coarse_lds_bytes(g, nw[b], vec, blk));
-    }
-    if (coarse_batch_capacity(lds_need) < used) {
-      // a larger LDS lowered the occupancy: drop the staging everywhere
-      lds_need = 0;
-      for (int b = 0; b < n; ++b) {
-        shape[b].vec_lds = shape[b].blk_lds = 0;
-        lds_need = std::max(lds_need, coarse_lds_bytes(jobs[b]->L->g, nw[b], 0, 0));
-      }
-      if (coarse_batch_capacity(lds_need) < used) return TL_E_DEVICE;
-    }
-    lds = lds_need;
+    std::vector<const Geo*> gs(n);
+    for (int b = 0; b < n; ++b) gs[b] = &jobs[b]->L->g;
+    std::vector<int> nw;
+    std::vector<CoarseShape> shape;
+    if (!plan_coarse(gs, &nw, &shape, &lds)) return TL_E_BUDGET;
     std::vector<int> wl;
     nsets = 0;
     for (int b = 0; b < n; ++b) {
@@ -270,6 +283,69 @@ void drop_work(Job* j) {
   j->w = nullptr;
 }
 
+// Run one co-resident group of a tl_solve_batch call to completion: start
+// every solve, build the fused tables, capture one chunk of iterations in a
+// hipGraph and replay it until every lattice of the group has stopped, then
+// copy out and certify each result (marking its job finished).
+tl_status run_group(std::vector<Job*>& group, const std::map<tl_lattice*, int>& seen,
+                    const Opts& o, hipStream_t st) {
+  tl_status first = TL_OK;
+  FusedBatch fb;
+  for (Job* j : group) {
+    if (seen.at(j->L) == 1) {   // a lattice that appears once uses its cached work space
+      tl_status err = TL_OK;
+      j->w = lattice_work(j->L, o.mixed, o.max_iters + 1, &err);
+      j->own_work = false;
+      if (!j->w) { first = err; break; }
+    }
+    first = alloc_and_start(j, st);
+    if (first != TL_OK) break;
+    fb.jobs.push_back(j);
+  }
+  if (first == TL_OK) first = fb.build(st);
+  if (first == TL_OK) {
+    const int chunk = 8;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (use_graph) {
+      tl_status s = TL_OK;
+      for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb.enqueue_iteration(st);
+      const bool ended = hipStreamEndCapture(st, &graph) == hipSuccess;
+      use_graph = s == TL_OK && ended &&
+                  hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (!use_graph) (void)hipGetLastError();
+    }
+    int rounds = 0;
+    const int max_rounds = o.max_iters / chunk + 2;
+    const int n = (int)group.size();
+    for (;;) {
+      tl_status s = TL_OK;
+      if (use_graph) {
+        s = hipGraphLaunch(exec, st) == hipSuccess ? TL_OK : TL_E_DEVICE;
+      } else {
+        for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb.enqueue_iteration(st);
+      }
+      if (s == TL_OK) s = fb.read_ctrl(st);
+      if (s != TL_OK) { first = s; break; }
+      bool all = true;
+      for (int b = 0; b < n; ++b) all = all && (fb.h_ctrl[b].done || fb.h_ctrl[b].err);
+      if (all) break;
+      if (++rounds > max_rounds) { first = TL_E_DEVICE; break; }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (first == TL_OK) {
+      for (int b = 0; b < n; ++b) {
+        finish_job(group[b], fb.h_ctrl[b], st);
+        group[b]->finished = true;
+      }
+    }
+  }
+  fb.release();
+  return first;
+}
+
 }  // namespace
 
 }  // namespace tl
@@ -315,6 +391,13 @@ void server_loop(tl_server* S) {
         Job* j = S->queue.front();
         const size_t b = job_bytes(j);
         if (S->used + b > S->budget) break;
+        // the fused batch of the job's precision must stay co-resident
+        std::vector<Job*> group;
+        for (Job* k : live[j->o.mixed ? 1 : 0]) group.push_back(k);
+        for (Job* k : admitted)
+          if (k->o.mixed == j->o.mixed) group.push_back(k);
+        group.push_back(j);
+        if (group.size() > 1 && !coresident(group)) break;
         S->queue.pop_front();
         S->used += b;
         admitted.push_back(j);
@@ -405,58 +488,30 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
   (void)hipEventCreate(&e1);
   (void)hipEventRecord(ev_in, user);
   (void)hipStreamWaitEvent(st, ev_in, 0);
+  (void)hipEventRecord(e0, st);
+  // Lattices are taken in order into groups whose upper-level workgroups
+  // can all be co-resident; the groups run one after another.
   tl_status first = TL_OK;
-  FusedBatch fb;
-  for (int i = 0; i < n && first == TL_OK; ++i) {
+  std::vector<Job*> pending;
+  for (int i = 0; i < n; ++i) {
     Job& j = jobs[i];
     j.L = lats[i];
     j.f = f_dev[i];
     j.u = u_dev[i];
     j.o = o;
     j.lock_lattice = false;
-    if (seen[j.L] == 1) {   // a lattice that appears once uses its cached work space
-      tl_status err = TL_OK;
-      j.w = lattice_work(j.L, o.mixed, o.max_iters + 1, &err);
-      j.own_work = false;
-      if (!j.w) { first = err; break; }
-    }
-    first = alloc_and_start(&j, st);
-    if (first == TL_OK) fb.jobs.push_back(&j);
+    pending.push_back(&j);
   }
-  if (first == TL_OK) first = fb.build(st);
-  (void)hipEventRecord(e0, st);
-  if (first == TL_OK) {
-    // capture one chunk of iterations; replay until every lattice stopped
-    const int chunk = 8;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    bool use_graph = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (use_graph) {
-      tl_status s = TL_OK;
-      for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb.enqueue_iteration(st);
-      const bool ended = hipStreamEndCapture(st, &graph) == hipSuccess;
-      use_graph = s == TL_OK && ended &&
-                  hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-      if (!use_graph) (void)hipGetLastError();
+  size_t next = 0;
+  while (next < pending.size() && first == TL_OK) {
+    std::vector<Job*> group;
+    while (next < pending.size()) {
+      group.push_back(pending[next]);
+      if (group.size() > 1 && !coresident(group)) { group.pop_back(); break; }
+      ++next;
     }
-    int rounds = 0;
-    const int max_rounds = o.max_iters / chunk + 2;
-    for (;;) {
-      tl_status s = TL_OK;
-      if (use_graph) {
-        s = hipGraphLaunch(exec, st) == hipSuccess ? TL_OK : TL_E_DEVICE;
-      } else {
-        for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb.enqueue_iteration(st);
-      }
-      if (s == TL_OK) s = fb.read_ctrl(st);
-      if (s != TL_OK) { first = s; break; }
-      bool all = true;
-      for (int b = 0; b < n; ++b) all = all && (fb.h_ctrl[b].done || fb.h_ctrl[b].err);
-      if (all) break;
-      if (++rounds > max_rounds) { first = TL_E_DEVICE; break; }
-    }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    if (group.empty()) { first = TL_E_BUDGET; break; }   // one lattice that never fits
+    first = run_group(group, seen, o, st);
   }
   (void)hipEventRecord(e1, st);
   (void)hipEventSynchronize(e1);
@@ -464,11 +519,6 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
   (void)hipEventElapsedTime(&ms, e0, e1);
   for (int i = 0; i < n; ++i) {
     Job& j = jobs[i];
-    const bool ran = i < (int)fb.jobs.size() && fb.h_ctrl;
-    if (first == TL_OK && ran && (fb.h_ctrl[i].done || fb.h_ctrl[i].err)) {
-      finish_job(&j, fb.h_ctrl[i], st);
-      j.finished = true;
-    }
     if (!j.finished) j.status = first != TL_OK ? first : TL_E_DEVICE;
     j.info.status = j.status;
     j.info.ms = ms;
@@ -476,7 +526,6 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
     if (j.status != TL_OK && first == TL_OK) first = j.status;
     drop_work(&j);
   }
-  fb.release();
   (void)hipEventRecord(ev_out, st);
   (void)hipStreamWaitEvent(user, ev_out, 0);
   (void)hipStreamSynchronize(st);
@@ -513,7 +562,7 @@ tl_status tl_submit(tl_server* S, tl_lattice* L, const double* f_dev, double* u_
   resolve_opts(opts, &j->o);
   j->o.trace = nullptr;
   j->o.profile = 0;
-  if (job_bytes(j) > S->budget) { delete j; return TL_E_BUDGET; }
+  if (job_bytes(j) > S->budget || !coresident({j})) { delete j; return TL_E_BUDGET; }
   j->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lock(S->mu);

@@ -101,3 +101,65 @@ def test_server_budget_limits():
         tl.tl_submit(srv, lats[2], fs[2], u, precision=1, rtol=1e-9)
     assert ei.value.status == tl.TL_E_BUDGET
     srv.close()
+
+
+# Four 1500 x 1500 lattices with 32 x 32 sets (47 x 47 = 2209 sets each) take
+# ceil(2209 / 16) = 139 upper-level workgroups apiece, 556 together: more
+# than the device can hold co-resident, so a batch of them runs as groups
+# and a server admits them a few at a time.
+BIG = 1500
+
+
+@pytest.fixture(scope="module")
+def big_mix():
+    insts, lats, fs = [], [], []
+    for k in range(4):
+        inst = make_instance(BIG, BIG, seed=500 + k, ea="lognormal")
+        insts.append(inst)
+        lats.append(tl.tl_lattice_create(BIG, BIG, ea=inst.ea, fixed=inst.fixed, set_edge=32))
+        fs.append(torch.from_numpy(inst.f).cuda())
+    for nx, ny, E, ea, seed in SHAPES[:3]:
+        inst = make_instance(nx, ny, seed=seed, ea=ea)
+        insts.append(inst)
+        lats.append(tl.tl_lattice_create(nx, ny, ea=inst.ea, fixed=inst.fixed, set_edge=E))
+        fs.append(torch.from_numpy(inst.f).cuda())
+    alone = []
+    for lat, f in zip(lats, fs):
+        u = torch.zeros_like(f)
+        tl.tl_solve(lat, f, u, precision=1, rtol=1e-8)
+        alone.append(u)
+    return insts, lats, fs, alone
+
+
+def test_batch_beyond_coresident_capacity(big_mix):
+    insts, lats, fs, alone = big_mix
+    us = [torch.zeros_like(f) for f in fs]
+    st, infos = tl.tl_solve_batch(lats, fs, us, precision=1, rtol=1e-8)
+    assert st == tl.TL_OK
+    for u, ua, info in zip(us, alone, infos):
+        assert info["status"] == tl.TL_OK
+        assert max(info["rel_res_l1"], info["rel_res_l2"]) <= 1e-8
+        assert torch.equal(u, ua)
+
+
+def test_server_admits_by_coresidency(big_mix):
+    insts, lats, fs, alone = big_mix
+    srv = tl.tl_server_create(1 << 36, 8)
+    us = [torch.zeros_like(f) for f in fs]
+    tickets = [tl.tl_submit(srv, lat, f, u, precision=1, rtol=1e-8)
+               for lat, f, u in zip(lats, fs, us)]
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets) and time.time() - t0 < 100:
+        for tk in tickets:
+            if tk not in done:
+                st, info = tl.tl_poll(srv, tk)
+                if st != tl.TL_PENDING:
+                    done[tk] = (st, info)
+        time.sleep(0.001)
+    srv.close()
+    assert len(done) == len(tickets)
+    for tk, u, ua in zip(tickets, us, alone):
+        st, info = done[tk]
+        assert st == tl.TL_OK
+        assert torch.equal(u, ua)
