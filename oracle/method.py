@@ -79,22 +79,42 @@ def make_sets(nx: int, ny: int, E: int, rep_shift=(0.0, 0.0)) -> Sets:
     return Sets(nx, ny, E, mx, my, of_node, xc, yc, E / 2.0)
 
 
+def relaxation_region(sets: Sets, I: int, overlap: int) -> np.ndarray:
+    """Node ids of set I's relaxation region: its tile, widened by `overlap`
+    nodes on every side in index space and clipped to the lattice (section
+    2.2 end: relaxing a larger region around the set)."""
+    E, nx, ny = sets.E, sets.nx, sets.ny
+    i0, j0 = (I % sets.mx) * E, (I // sets.mx) * E
+    i1, j1 = min(i0 + E, nx), min(j0 + E, ny)
+    a0, a1 = max(i0 - overlap, 0), min(i1 + overlap, nx)
+    b0, b1 = max(j0 - overlap, 0), min(j1 + overlap, ny)
+    jj, ii = np.meshgrid(np.arange(b0, b1), np.arange(a0, a1), indexing="ij")
+    return (jj * nx + ii).reshape(-1)
+
+
 class LocalSolver:
     """Exact local relaxation of Eq. 12 for every set.
 
-    For set I, k^Inner is the block of K on the set's free DOFs (its entries
-    are those of the global matrix, section 2.2), so
+    For set I, k^Inner is the block of K on the free DOFs of the relaxation
+    region (its entries are those of the global matrix, section 2.2), so
         k^Inner u^RD = p^Inner - k^Outer u^Outer,old
-    gives u^RD - u^old = (k^Inner)^-1 (p - K u^old)|_I.  The factors are
-    computed once and reused, as section 2.2 describes."""
+    gives u^RD - u^old = (k^Inner)^-1 (p - K u^old)|_region.  With overlap 0
+    the region is the set itself; with overlap w > 0 it is the set widened by
+    w nodes (section 2.2 end) and the increment is kept on the set's own
+    DOFs only, so the modes of different sets still have disjoint supports.
+    The factors are computed once and reused, as section 2.2 describes."""
 
-    def __init__(self, sys_: System, sets: Sets):
-        self.idx = []
+    def __init__(self, sys_: System, sets: Sets, overlap: int = 0):
+        self.idx = []      # region free DOFs
+        self.own = []      # positions (within idx) of the set's own DOFs
         self.lu = []
         dof_set = np.repeat(sets.of_node, 2)
         for I in range(sets.M):
-            idx = np.flatnonzero((dof_set == I) & sys_.free)
+            nodes = relaxation_region(sets, I, overlap)
+            dofs = np.sort(np.concatenate([2 * nodes, 2 * nodes + 1]))
+            idx = dofs[sys_.free[dofs]]
             self.idx.append(idx)
+            self.own.append(np.flatnonzero(dof_set[idx] == I))
             if idx.size:
                 kin = sys_.K[idx][:, idx].tocsc()
                 self.lu.append(spla.splu(kin))
@@ -104,9 +124,9 @@ class LocalSolver:
     def relax(self, r: np.ndarray) -> np.ndarray:
         """Relaxation increment (Eq. 13) of every set, stacked into one vector."""
         d = np.zeros_like(r)
-        for idx, lu in zip(self.idx, self.lu):
+        for idx, own, lu in zip(self.idx, self.own, self.lu):
             if lu is not None:
-                d[idx] = lu.solve(r[idx])
+                d[idx[own]] = lu.solve(r[idx])[own]
         return d
 
 
@@ -180,10 +200,10 @@ class Step:
 class Method:
     """Outer loop of the hierarchical solver with exact inner solves."""
 
-    def __init__(self, sys_: System, sets: Sets):
+    def __init__(self, sys_: System, sets: Sets, overlap: int = 0):
         self.sys = sys_
         self.sets = sets
-        self.local = LocalSolver(sys_, sets)
+        self.local = LocalSolver(sys_, sets, overlap)
 
     def step(self, u_old: np.ndarray) -> Step:
         r = residual(self.sys, u_old)

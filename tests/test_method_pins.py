@@ -114,3 +114,76 @@ def test_planted_wrong_gradient_mode_is_caught(monkeypatch):
     st_bad = m.step(S.u_c.copy())
     g = st_good.U.T @ residual(S, st_bad.u_new)
     assert np.linalg.norm(g) > 1e-6 * np.linalg.norm(st_good.U.T @ st_good.r)
+
+
+# ------------------------------------------- overlapping relaxation regions
+# Section 2.2 (end): a set may be relaxed on a larger region around it.  The
+# reading here: the region is the set's tile widened by w nodes on every side
+# (clipped to the lattice), solved with everything outside it held fixed, and
+# the increment is kept on the set's own DOFs.
+
+def _region_by_loops(nx, ny, E, I, w):
+    """Free-or-not node ids of set I's widened tile, by explicit loops."""
+    mx = -(-nx // E)
+    i0, j0 = (I % mx) * E, (I // mx) * E
+    out = []
+    for j in range(ny):
+        for i in range(nx):
+            di = max(i0 - i, 0, i - (min(i0 + E, nx) - 1))
+            dj = max(j0 - j, 0, j - (min(j0 + E, ny) - 1))
+            if di <= w and dj <= w:
+                out.append(j * nx + i)
+    return out
+
+
+@pytest.mark.parametrize("w", [1, 2, 5])
+def test_overlap_increment_equals_dense_region_solve(w):
+    nx, ny, E = 13, 11, 4
+    inst = make_instance(nx, ny, seed=21, ea="lognormal")
+    S = system_of(inst)
+    sets = om.make_sets(nx, ny, E)
+    r = residual(S, S.u_c.copy())
+    d = om.LocalSolver(S, sets, overlap=w).relax(r)
+    Kd = S.K.toarray()
+    for I in (0, 5, sets.M - 1):
+        nodes = _region_by_loops(nx, ny, E, I, w)
+        dofs = [2 * n + c for n in nodes for c in (0, 1) if S.free[2 * n + c]]
+        x = np.linalg.solve(Kd[np.ix_(dofs, dofs)], r[dofs])
+        own = [k for k, q in enumerate(dofs) if sets.of_node[q // 2] == I]
+        got = d[[dofs[k] for k in own]]
+        assert np.allclose(got, x[own], rtol=1e-11, atol=1e-14 * np.abs(x).max())
+        # nothing outside the set
+        mine = np.repeat(sets.of_node == I, 2)
+        assert np.all(d[mine & ~np.isin(np.arange(d.size), dofs)] == 0.0)
+
+
+def test_overlap_covering_lattice_converges_in_one_iteration():
+    # every region is the whole lattice: each set's increment is the exact
+    # correction restricted to the set, and a_7 = 1 on every set rebuilds it
+    inst = make_instance(30, 22, seed=22, ea="lognormal")
+    S = system_of(inst)
+    m = om.Method(S, om.make_sets(30, 22, 8), overlap=40)
+    assert m.sets.M == 12
+    st = m.step(S.u_c.copy())
+    assert max(rel_residuals(S, st.u_new)) <= 1e-11
+
+
+def test_overlap_energy_monotone_and_converges():
+    inst = make_instance(40, 33, seed=23, ea="lognormal")
+    S = system_of(inst)
+    m0 = om.Method(S, om.make_sets(40, 33, 16))
+    m3 = om.Method(S, om.make_sets(40, 33, 16), overlap=3)
+    u3, it3, hist3 = m3.run(tol=1e-11, max_iters=400)
+    _, it0, _ = m0.run(tol=1e-11, max_iters=400)
+    Pi = [h[2] for h in hist3]
+    assert all(Pi[k + 1] <= Pi[k] + 1e-13 * abs(Pi[k]) for k in range(len(Pi) - 1))
+    ref = solve(S)
+    assert np.linalg.norm(u3 - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert it3 < it0          # the larger region relaxes better (section 2.2 end)
+
+
+def test_planted_region_off_by_one_is_caught(monkeypatch):
+    real = om.relaxation_region
+    monkeypatch.setattr(om, "relaxation_region", lambda sets, I, w: real(sets, I, max(w - 1, 0)))
+    with pytest.raises(AssertionError):
+        test_overlap_increment_equals_dense_region_solve(2)
