@@ -93,13 +93,17 @@ typedef struct {
     tl_precision precision;
     double rtol;               /* stop when max(R1, R2) <= rtol (Eq. 19, both norms) */
     int32_t max_iters;         /* outer iterations; 0 = library default             */
-    int32_t inner_iters;       /* relaxation PCG sweeps per set; 0 = default         */
-    int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default         */
-    double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default    */
+    int32_t inner_iters;       /* relaxation PCG sweeps per set; 0 = default (10)    */
+    int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default (100)   */
+    double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default 0.1 */
     int32_t warm_start;        /* 1: start from the free DOFs of u (else from 0)     */
     tl_trace* trace;           /* NULL, or diagnostics to fill                       */
     int32_t profile;           /* 1: time every kernel launch with HIP events on the
                                   solve's stream (fills the *_ms fields of tl_info)  */
+    int32_t overlap;           /* relax each set on its tile widened by this many
+                                  nodes on every side, keeping the increment on the
+                                  set (section 2.2 end): 1, 2 or 4; -1 = the set
+                                  alone; 0 = library default (2)                    */
 } tl_opts;
 
 typedef struct {

@@ -119,8 +119,12 @@ struct FusedBatch {
   std::vector<Job*> jobs;
   std::vector<BatchEntry> h;
   BatchEntry* d_entries = nullptr;
-  int* d_tile_lat[3] = {nullptr, nullptr, nullptr};   // set edges 16, 32, 64
-  int ntiles[3] = {0, 0, 0};
+  // tile launches: one per (set edge, overlap) present
+  static constexpr int kEdges[3] = {16, 32, 64};
+  static constexpr int kOverlaps[4] = {0, 1, 2, 4};
+  static constexpr int kGroups = 12;
+  int* d_tile_lat[kGroups] = {};
+  int ntiles[kGroups] = {};
   int* d_set_lat = nullptr;
   int nsets = 0;
   int* d_wg_lat = nullptr;
@@ -132,11 +136,13 @@ struct FusedBatch {
   bool mixed = false;
 
   void release_tables() {
-    for (void* p : {(void*)d_entries, (void*)d_tile_lat[0], (void*)d_tile_lat[1],
-                    (void*)d_tile_lat[2], (void*)d_set_lat, (void*)d_wg_lat})
+    for (int k = 0; k < kGroups; ++k) {
+      if (d_tile_lat[k]) (void)hipFree(d_tile_lat[k]);
+      d_tile_lat[k] = nullptr;
+    }
+    for (void* p : {(void*)d_entries, (void*)d_set_lat, (void*)d_wg_lat})
       if (p) (void)hipFree(p);
     d_entries = nullptr;
-    d_tile_lat[0] = d_tile_lat[1] = d_tile_lat[2] = nullptr;
     d_set_lat = d_wg_lat = nullptr;
   }
   void release() {
@@ -148,7 +154,9 @@ struct FusedBatch {
     cap = 0;
   }
 
-  static int edge_slot(int E) { return E == 16 ? 0 : E == 32 ? 1 : 2; }
+  static int group_slot(int E, int ov) {
+    return (E == 16 ? 0 : E == 32 ? 1 : 2) * 4 + (ov == 0 ? 0 : ov == 1 ? 1 : ov == 2 ? 2 : 3);
+  }
 
   // Build the entry and lookup tables for the current jobs (all of whose
   // work spaces exist and were initialised).
@@ -158,7 +166,7 @@ struct FusedBatch {
     if (n == 0) return TL_OK;
     mixed = jobs[0]->o.mixed;
     h.assign(n, BatchEntry{});
-    std::vector<int> tl[3], sl;
+    std::vector<int> tl[kGroups], sl;
     std::vector<const Geo*> gs(n);
     for (int b = 0; b < n; ++b) gs[b] = &jobs[b]->L->g;
     std::vector<int> nw;
@@ -177,7 +185,7 @@ struct FusedBatch {
       e.ca.nwg = nw[b];
       e.ca.vec_lds = shape[b].vec_lds;
       e.ca.blk_lds = shape[b].blk_lds;
-      const int slot = edge_slot(g.E);
+      const int slot = group_slot(g.E, j->o.overlap);
       e.tile0 = (int)tl[slot].size();
       for (int t = 0; t < g.M; ++t) tl[slot].push_back(b);
       e.set0 = nsets;
@@ -195,7 +203,7 @@ struct FusedBatch {
     };
     void* p;
     TB_TRY(up(h.data(), n * sizeof(BatchEntry), &p)); d_entries = (BatchEntry*)p;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kGroups; ++k) {
       ntiles[k] = (int)tl[k].size();
       TB_TRY(up(tl[k].data(), tl[k].size() * sizeof(int), &p)); d_tile_lat[k] = (int*)p;
     }
@@ -216,9 +224,9 @@ struct FusedBatch {
 
   // One outer iteration of every lattice in the batch.
   tl_status enqueue_iteration(hipStream_t st) const {
-    static const int edges[3] = {16, 32, 64};
-    for (int k = 0; k < 3; ++k)
-      TB_TRY(launch_tile_batch(mixed, edges[k], d_entries, d_tile_lat[k], ntiles[k], st));
+    for (int k = 0; k < kGroups; ++k)
+      TB_TRY(launch_tile_batch(mixed, kEdges[k / 4], kOverlaps[k % 4], d_entries, d_tile_lat[k],
+                               ntiles[k], st));
     TB_TRY(launch_offdiag_batch(mixed, d_entries, d_set_lat, nsets, st));
     TB_TRY(launch_blockinv_batch(d_entries, d_set_lat, nsets, st));
     TB_TRY(launch_coarse_batch(d_entries, d_wg_lat, nwg, lds, st));
@@ -468,7 +476,7 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
     if (!lats[i] || !f_dev[i] || !u_dev[i]) return TL_E_INVAL;
   if (n == 0) return TL_OK;
   Opts o;
-  resolve_opts(opts, &o);
+  if (resolve_opts(opts, &o) != TL_OK) return TL_E_INVAL;
   o.trace = nullptr;
   o.profile = 0;
   hipStream_t user = (hipStream_t)hip_stream;
@@ -559,7 +567,7 @@ tl_status tl_submit(tl_server* S, tl_lattice* L, const double* f_dev, double* u_
   j->L = L;
   j->f = f_dev;
   j->u = u_dev;
-  resolve_opts(opts, &j->o);
+  if (resolve_opts(opts, &j->o) != TL_OK) { delete j; return TL_E_INVAL; }
   j->o.trace = nullptr;
   j->o.profile = 0;
   if (job_bytes(j) > S->budget || !coresident({j})) { delete j; return TL_E_BUDGET; }

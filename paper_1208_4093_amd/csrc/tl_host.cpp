@@ -136,16 +136,29 @@ CoarseShape coarse_shape(const Geo& g) {
   return c;
 }
 
-void resolve_opts(const tl_opts* o, Opts* r) {
+// Defaults when the caller leaves a field at 0.  Measured on 1024^2 (unit EA,
+// 32 x 32 sets), 2048^2 and 4096^2 (lognormal EA, 32 and 64 sets) to 1e-8:
+// widening each relaxation region by 2 nodes cuts the outer iterations 2-3x
+// for 1.3-1.9x more tile time, and capping the upper-level PCG at 100
+// iterations (relative tolerance 0.1) avoids long solves whose extra
+// accuracy the outer iteration does not use; together about 2x faster.
+constexpr int kDefaultOverlap = 2;
+constexpr int kDefaultCoarseIters = 100;
+
+tl_status resolve_opts(const tl_opts* o, Opts* r) {
   r->mixed = o && o->precision == TL_MIXED;
   r->rtol = o && o->rtol > 0.0 ? o->rtol : 1e-8;
   r->max_iters = o && o->max_iters > 0 ? o->max_iters : 20000;
   r->inner = o && o->inner_iters > 0 ? o->inner_iters : 10;
-  r->coarse_iters = o && o->coarse_iters > 0 ? o->coarse_iters : 300;
+  r->overlap = !o || o->overlap == 0 ? kDefaultOverlap : (o->overlap < 0 ? 0 : o->overlap);
+  r->coarse_iters = o && o->coarse_iters > 0 ? o->coarse_iters : kDefaultCoarseIters;
   r->coarse_rtol = o && o->coarse_rtol > 0.0 ? o->coarse_rtol : 0.1;
   r->warm = o ? o->warm_start : 0;
   r->trace = o ? o->trace : nullptr;
   r->profile = o ? o->profile : 0;
+  if (!(r->rtol > 0.0) || r->max_iters < 0 || r->inner < 0 || !tile_overlap_supported(r->overlap))
+    return TL_E_INVAL;
+  return TL_OK;
 }
 
 // Arguments of one outer iteration's kernels for one solve (fixed for the
@@ -220,7 +233,7 @@ tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const d
   CoarseArgs ca;
   make_iteration_args(L, w, o, f, &ta, &oa, &ba, &ca);
   if (ev) TL_TRY(hipEventRecord(ev[0], st));
-  TL_TRY(launch_tile(o.mixed, L->g, L->ea, L->mask, ta, st));
+  TL_TRY(launch_tile(o.mixed, o.overlap, L->g, L->ea, L->mask, ta, st));
   if (ev) TL_TRY(hipEventRecord(ev[1], st));
   TL_TRY(launch_offdiag(o.mixed, L->g, L->ea, L->mask, oa, st));
   TL_TRY(launch_blockinv(L->g, ba, st));
@@ -508,8 +521,7 @@ tl_status tl_solve(tl_lattice* L, const double* f_dev, double* u_dev, const tl_o
                    tl_info* info, void* hip_stream) {
   if (!L || !f_dev || !u_dev) return TL_E_INVAL;
   Opts o;
-  resolve_opts(opts, &o);
-  if (!(o.rtol > 0.0) || o.max_iters < 0 || o.inner < 0) return TL_E_INVAL;
+  if (resolve_opts(opts, &o) != TL_OK) return TL_E_INVAL;
   std::lock_guard<std::mutex> lock(L->mu);
   tl_status err = TL_OK;
   Work* w = lattice_work(L, o.mixed, o.max_iters + 1, &err);

@@ -142,15 +142,16 @@ struct BatchEntry {
 };
 
 // Launchers (tl_kernels.hip).  All are asynchronous on `stream`.
-hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
+hipError_t launch_tile(bool mixed, int ov, const Geo& g, const float* ea, const uint8_t* mask,
                        const TileArgs& a, hipStream_t stream);
+bool tile_overlap_supported(int ov);
 hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
                           const OffArgs& a, hipStream_t stream);
 hipError_t launch_blockinv(const Geo& g, const BlockArgs& a, hipStream_t stream);
 hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream);
 size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds);
 // Fused launches over a batch (entries and lookup tables in device memory).
-hipError_t launch_tile_batch(bool mixed, int E, const BatchEntry* B, const int* tile_lat,
+hipError_t launch_tile_batch(bool mixed, int E, int ov, const BatchEntry* B, const int* tile_lat,
                              int ntiles, hipStream_t stream);
 hipError_t launch_offdiag_batch(bool mixed, const BatchEntry* B, const int* set_lat, int nsets,
                                 hipStream_t stream);

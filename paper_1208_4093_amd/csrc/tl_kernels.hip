@@ -109,16 +109,24 @@ template <> __device__ __forceinline__ double2 mk2<double>(double x, double y) {
 // ---------------------------------------------------------------------------
 // Tile kernel: update + residual + local relaxation + set's upper-level rows.
 // ---------------------------------------------------------------------------
-template <typename T, int E, int NT>
+//
+// OV is the overlap of the relaxation region (section 2.2 end): the set's
+// tile widened by OV nodes on every side, clipped to the lattice.  The update
+// and the residual cover the region (plus a one-node ring for the stencil),
+// the relaxation solves on the region's free DOFs with everything outside it
+// held fixed, and the increment, the stop-test norms and the upper-level rows
+// use the set's own nodes only.  OV = 0 is the plain set.
+template <typename T, int E, int NT, int OV>
 __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict__ ea,
                                           const uint8_t* __restrict__ mask, const TileArgs& A,
                                           const int tile) {
   using T2 = typename V2<T>::type;
-  constexpr int NPT = E * E / NT;
-  constexpr int W = E + 2;
+  constexpr int R = E + 2 * OV;                 // region edge before clipping
+  constexpr int NPT = (R * R + NT - 1) / NT;
+  constexpr int W = R + 2;
   constexpr int NW = NT / 64;
-  static_assert(E * E % NT == 0, "tile must split evenly over the workgroup");
-  __shared__ double2 su[W * W];                 // u over tile + halo, then T2 p / delta
+  static_assert(OV + 1 <= E, "the region's ring must stay within the neighbouring sets");
+  __shared__ double2 su[W * W];                 // u over region + ring, then T2 p / delta
   __shared__ double sa[9][Q];                   // coefficients of the 3x3 set neighbourhood
   __shared__ double sred[3][NW];
   __shared__ double sacc[NW][KROW + 3];
@@ -134,6 +142,8 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   const int I = tile % g.mx, J = tile / g.mx;
   const int i0 = I * E, j0 = J * E;
   const int tw = min(E, g.nx - i0), th = min(E, g.ny - j0);
+  const int ri0 = max(i0 - OV, 0), rj0 = max(j0 - OV, 0);      // relaxation region
+  const int rw = min(i0 + tw + OV, g.nx) - ri0, rh = min(j0 + th + OV, g.ny) - rj0;
   const int t = threadIdx.x;
   const size_t plane = (size_t)(g.ny + 2) * g.pitch;
   const double inv_hs = 2.0 / E;
@@ -146,13 +156,13 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   }
   __syncthreads();
 
-  // 1. u_new = u_old + sum_m a_m u_hat_m (Eq. 3) on the tile and its halo.
-  //    All loads of a thread's region nodes are issued before any is used,
-  //    so the phase costs one memory latency instead of one per node.
+  // 1. u_new = u_old + sum_m a_m u_hat_m (Eq. 3) on the region and its ring.
+  //    All loads of a thread's nodes are issued before any is used, so the
+  //    phase costs one memory latency instead of one per node.
   {
-    constexpr int RIT = ((E + 2) * (E + 2) + NT - 1) / NT;
+    constexpr int RIT = (W * W + NT - 1) / NT;
     const T2* din = reinterpret_cast<const T2*>(d_in_v);
-    const int rw = tw + 2, rn = (tw + 2) * (th + 2);
+    const int ew = rw + 2, rn = (rw + 2) * (rh + 2);
     double2 ul[RIT];
     T2 dl[RIT];
     uint8_t ml[RIT];
@@ -163,7 +173,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       ul[k] = make_double2(0.0, 0.0);
       dl[k] = mk2<T>((T)0, (T)0);
       if (idx < rn) {
-        const size_t p = pidx(g, i0 - 1 + idx % rw, j0 - 1 + idx / rw);
+        const size_t p = pidx(g, ri0 - 1 + idx % ew, rj0 - 1 + idx / ew);
         ul[k] = u_in[p];
         ml[k] = mask[p];
         dl[k] = din[p];
@@ -173,12 +183,11 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     for (int k = 0; k < RIT; ++k) {
       const int idx = t + k * NT;
       if (idx >= rn) continue;
-      const int ri = idx % rw, rj = idx / rw;
-      const int gi = i0 - 1 + ri, gj = j0 - 1 + rj;
+      const int ri = idx % ew, rj = idx / ew;
+      const int gi = ri0 - 1 + ri, gj = rj0 - 1 + rj;
       double2 u = ul[k];
-      if (!ml[k]) {
-        const int dI = ri == 0 ? -1 : (ri == tw + 1 ? 1 : 0);
-        const int dJ = rj == 0 ? -1 : (rj == th + 1 ? 1 : 0);
+      if (!ml[k]) {            // a lattice node (the padding ring is masked)
+        const int dI = gi / E - I, dJ = gj / E - J;
         const int oi0 = (I + dI) * E, oj0 = (J + dJ) * E;
         double xi, eta;
         set_coords(gi, gj, oi0, oj0, min(E, g.nx - oi0), min(E, g.ny - oj0), inv_hs, xi, eta);
@@ -188,7 +197,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         u.y += c[1] + c[4] * xi + c[5] * eta + w * (double)dl[k].y;
       }
       su[rj * W + ri] = u;
-      if (ri >= 1 && ri <= tw && rj >= 1 && rj <= th) u_out[pidx(g, gi, gj)] = u;
+      if (gi >= i0 && gi < i0 + tw && gj >= j0 && gj < j0 + th) u_out[pidx(g, gi, gj)] = u;
     }
   }
   __syncthreads();
@@ -197,7 +206,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   float kk[NPT][6];
   double2 r[NPT];
   T dxx[NPT], dxy[NPT], dyy[NPT], ixx[NPT], ixy[NPT], iyy[NPT];
-  bool act[NPT];
+  bool act[NPT], own[NPT];
   double part[10];   // P1..P6, sum|r|, sum r^2, sum|f|, sum f^2
 #pragma unroll
   for (int v = 0; v < 10; ++v) part[v] = 0.0;
@@ -206,30 +215,33 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   // all of the thread's loads first (one memory latency), then the arithmetic
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
-    const int n = t + k * NT, li = n % E, lj = n / E;
+    const int n = t + k * NT, li = n % R, lj = n / R;
     act[k] = false;
+    own[k] = false;
     fl[k] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int b = 0; b < 6; ++b) kk[k][b] = 0.f;
-    if (li < tw && lj < th) {
-      const size_t p = pidx(g, i0 + li, j0 + lj);
+    if (n < R * R && li < rw && lj < rh) {
+      const int gi = ri0 + li, gj = rj0 + lj;
+      const size_t p = pidx(g, gi, gj);
       act[k] = mask[p] == 0;
+      own[k] = act[k] && gi >= i0 && gi < i0 + tw && gj >= j0 && gj < j0 + th;
       kk[k][0] = ea[p];
       kk[k][1] = ea[plane + p];
       kk[k][2] = ea[2 * plane + p];
       kk[k][3] = ea[p - 1];
       kk[k][4] = ea[plane + p - g.pitch];
       kk[k][5] = ea[2 * plane + p - g.pitch + 1];
-      fl[k] = A.f[(size_t)(j0 + lj) * g.nx + (i0 + li)];
+      fl[k] = A.f[(size_t)gj * g.nx + gi];
     }
   }
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
-    const int n = t + k * NT, li = n % E, lj = n / E;
+    const int n = t + k * NT, li = n % R, lj = n / R;
     r[k] = make_double2(0.0, 0.0);
     dxx[k] = dxy[k] = dyy[k] = ixx[k] = ixy[k] = iyy[k] = (T)0;
     if (!act[k]) continue;
-    const int gi = i0 + li, gj = j0 + lj;
+    const int gi = ri0 + li, gj = rj0 + lj;
     const size_t p = pidx(g, gi, gj);
     const int c = (lj + 1) * W + (li + 1);
     const double2 ua = su[c];
@@ -265,19 +277,21 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       }
     }
     r[k] = make_double2(rx, ry);
-    double xi, eta;
-    set_coords(gi, gj, i0, j0, tw, th, inv_hs, xi, eta);
-    part[0] += rx;
-    part[1] += ry;
-    part[2] += xi * rx;
-    part[3] += eta * rx;
-    part[4] += xi * ry;
-    part[5] += eta * ry;
-    part[6] += fabs(rx) + fabs(ry);
-    part[7] += rx * rx + ry * ry;
-    part[8] += fabs(fv.x) + fabs(fv.y);
-    part[9] += fv.x * fv.x + fv.y * fv.y;
     rmax = fmax(rmax, fmax(fabs(rx), fabs(ry)));
+    if (own[k]) {
+      double xi, eta;
+      set_coords(gi, gj, i0, j0, tw, th, inv_hs, xi, eta);
+      part[0] += rx;
+      part[1] += ry;
+      part[2] += xi * rx;
+      part[3] += eta * rx;
+      part[4] += xi * ry;
+      part[5] += eta * ry;
+      part[6] += fabs(rx) + fabs(ry);
+      part[7] += rx * rx + ry * ry;
+      part[8] += fabs(fv.x) + fabs(fv.y);
+      part[9] += fv.x * fv.x + fv.y * fv.y;
+    }
     // diagonal 2x2 block of k^Inner: sum over all six rods of k n n^T
     const double ka = (double)kk[k][0] + kk[k][3];
     const double kb = (double)kk[k][1] + kk[k][4];
@@ -303,15 +317,15 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       for (int w = 0; w < NW; ++w) s = t == 10 ? fmax(s, sacc[w][10]) : s + sacc[w][t];
       sfin[t] = s;
     }
-    // zero the relaxation buffer (tile, halo ring and inactive nodes)
+    // zero the relaxation buffer (region, its ring and inactive nodes)
     for (int idx = t; idx < W * W; idx += NT) sp[idx] = mk2<T>((T)0, (T)0);
     __syncthreads();
   }
   if (t < 6) A.force[(size_t)tile * Q + t] = sfin[t];
   if (t >= 6 && t < 10) A.nrm[(size_t)tile * NRM + (t - 6)] = sfin[t];
 
-  // 3. local relaxation: k^Inner delta = r on the set's free DOFs, neighbour
-  //    sets held fixed (Eq. 12 minus k^Inner u_old), by block-Jacobi PCG.
+  // 3. local relaxation: k^Inner delta = r on the region's free DOFs, the
+  //    rest held fixed (Eq. 12 minus k^Inner u_old), by block-Jacobi PCG.
   //    Float32 form: r is scaled by 2^-e (e from max|r|) before rounding.
   const double rm = sfin[10];
   const double scl = (sizeof(T) == 4 && rm > 0.0 && isfinite(rm)) ? ldexp(1.0, -ilogb(rm)) : 1.0;
@@ -331,7 +345,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     for (int k = 0; k < NPT; ++k) {
       if (!act[k]) continue;
       const int n = t + k * NT;
-      sp[(n / E + 1) * W + (n % E + 1)] = pp[k];
+      sp[(n / R + 1) * W + (n % R + 1)] = pp[k];
     }
     __syncthreads();
     double pq_part = 0.0;
@@ -339,7 +353,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     for (int k = 0; k < NPT; ++k) {
       if (!act[k]) { qq[k] = mk2<T>((T)0, (T)0); continue; }
       const int n = t + k * NT;
-      const int c = (n / E + 1) * W + (n % E + 1);
+      const int c = (n / R + 1) * W + (n % R + 1);
       const T2 pa = pp[k];
       T qx = dxx[k] * pa.x + dxy[k] * pa.y;
       T qy = dxy[k] * pa.x + dyy[k] * pa.y;
@@ -373,16 +387,18 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     }
   }
 
-  // 4. store the relaxation increment (mode 7 as stored, scaled in float32)
+  // 4. store the relaxation increment on the set's own nodes (mode 7 as
+  //    stored, scaled in float32); the buffer keeps it on those nodes only.
   {
     T2* dout = reinterpret_cast<T2*>(d_out_v);
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      const int n = t + k * NT, li = n % E, lj = n / E;
-      if (li < tw && lj < th) {
-        const T2 d = act[k] ? x[k] : mk2<T>((T)0, (T)0);
-        dout[pidx(g, i0 + li, j0 + lj)] = d;
-        if (act[k]) sp[(lj + 1) * W + (li + 1)] = d;
+      const int n = t + k * NT, li = n % R, lj = n / R;
+      if (n < R * R && li < rw && lj < rh) {
+        const int gi = ri0 + li, gj = rj0 + lj;
+        const T2 d = own[k] ? x[k] : mk2<T>((T)0, (T)0);
+        if (gi >= i0 && gi < i0 + tw && gj >= j0 && gj < j0 + th) dout[pidx(g, gi, gj)] = d;
+        if (act[k]) sp[(lj + 1) * W + (li + 1)] = d;   // zero on the overlap nodes
       }
     }
   }
@@ -400,13 +416,13 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   const double nvy[6] = {0.0, 0.0, kS3, kS3, kS3, kS3};
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
-    if (!act[k]) continue;
-    const int n = t + k * NT, li = n % E, lj = n / E;
+    if (!own[k]) continue;
+    const int n = t + k * NT, li = n % R, lj = n / R;
     const int c = (lj + 1) * W + (li + 1);
     const int off[6] = {1, -1, W, -W, W - 1, -W + 1};
     const int kidx[6] = {0, 3, 1, 4, 2, 5};
     double xi, eta;
-    set_coords(i0 + li, j0 + lj, i0, j0, tw, th, inv_hs, xi, eta);
+    set_coords(ri0 + li, rj0 + lj, i0, j0, tw, th, inv_hs, xi, eta);
     const double dax = (double)x[k].x, day = (double)x[k].y;
     const double ka = (double)kk[k][0] + kk[k][3];
     const double kb = (double)kk[k][1] + kk[k][4];
@@ -458,20 +474,20 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   }
 }
 
-template <typename T, int E, int NT>
+template <typename T, int E, int NT, int OV>
 __global__ __launch_bounds__(NT) void k_tile(Geo g, const float* __restrict__ ea,
                                              const uint8_t* __restrict__ mask, TileArgs A) {
-  tile_body<T, E, NT>(g, ea, mask, A, xcd_remap(blockIdx.x, gridDim.x));
+  tile_body<T, E, NT, OV>(g, ea, mask, A, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-// Fused launch over the tiles of several lattices with the same set edge:
-// tile_lat maps a launch-wide tile index to its lattice entry.
-template <typename T, int E, int NT>
+// Fused launch over the tiles of several lattices with the same set edge and
+// overlap: tile_lat maps a launch-wide tile index to its lattice entry.
+template <typename T, int E, int NT, int OV>
 __global__ __launch_bounds__(NT) void k_tile_batch(const BatchEntry* __restrict__ B,
                                                    const int* __restrict__ tile_lat) {
   const int gt = xcd_remap(blockIdx.x, gridDim.x);
   const BatchEntry& e = B[tile_lat[gt]];
-  tile_body<T, E, NT>(e.g, e.ea, e.mask, e.ta, gt - e.tile0);
+  tile_body<T, E, NT, OV>(e.g, e.ea, e.mask, e.ta, gt - e.tile0);
 }
 
 namespace {
@@ -1353,63 +1369,71 @@ int grid_for(size_t n, int nt, int cap) {
 }
 }  // namespace
 
-// Threads per tile workgroup for each set edge and precision (measured:
-// 256 for E = 32; 512 for E = 64 in float32, 1024 in float64, where 512
-// threads spill).  TL_TILE_THREADS overrides for tuning.
-static int tile_threads(int E, bool mixed) {
+// Threads per tile workgroup for each set edge, precision and overlap
+// (measured without overlap: 256 for E = 32; 512 for E = 64 in float32, 1024
+// in float64, where 512 threads spill).  With overlap the region holds
+// (E + 2 OV)^2 nodes: 256 threads for E = 16, 512 for 32, 1024 for 64.
+// TL_TILE_THREADS overrides for tuning.
+static int tile_threads(int E, bool mixed, int ov) {
   const char* v = getenv("TL_TILE_THREADS");
   const int env = v && *v ? atoi(v) : 0;
   if (E == 16) return 256;
+  if (ov > 0) return E == 32 ? (env == 256 || env == 512 ? env : 512) : 1024;
   if (E == 32) return env == 256 || env == 512 || env == 1024 ? env : 256;
   return env == 512 || env == 1024 ? env : (mixed ? 512 : 1024);
 }
 
-hipError_t launch_tile(bool mixed, const Geo& g, const float* ea, const uint8_t* mask,
+bool tile_overlap_supported(int ov) { return ov == 0 || ov == 1 || ov == 2 || ov == 4; }
+
+// Instantiations: (set edge, threads) for every overlap, float and double.
+#define TL_TILE_SHAPES(X, T, OV)                                   \
+  if (E == 16) X(T, 16, 256, OV);                                  \
+  else if (E == 32 && nt == 256) X(T, 32, 256, OV);                \
+  else if (E == 32 && nt == 512) X(T, 32, 512, OV);                \
+  else if (E == 32 && OV == 0) X(T, 32, 1024, 0);                  \
+  else if (E == 64 && nt == 512 && OV == 0) X(T, 64, 512, 0);      \
+  else if (E == 64) X(T, 64, 1024, OV);                            \
+  else return hipErrorInvalidValue;
+#define TL_TILE_OVERLAPS(X, T)                 \
+  if (ov == 0) { TL_TILE_SHAPES(X, T, 0) }     \
+  else if (ov == 1) { TL_TILE_SHAPES(X, T, 1) } \
+  else if (ov == 2) { TL_TILE_SHAPES(X, T, 2) } \
+  else if (ov == 4) { TL_TILE_SHAPES(X, T, 4) } \
+  else return hipErrorInvalidValue;
+
+hipError_t launch_tile(bool mixed, int ov, const Geo& g, const float* ea, const uint8_t* mask,
                        const TileArgs& a, hipStream_t stream) {
   const dim3 grid(g.M);
-  const int nt = tile_threads(g.E, mixed);
-#define TL_TILE(T, E, NT) hipLaunchKernelGGL((k_tile<T, E, NT>), grid, dim3(NT), 0, stream, g, ea, mask, a)
-#define TL_TILE_ALL(T)                                   \
-  if (g.E == 16) TL_TILE(T, 16, 256);                    \
-  else if (g.E == 32 && nt == 256) TL_TILE(T, 32, 256);  \
-  else if (g.E == 32 && nt == 512) TL_TILE(T, 32, 512);  \
-  else if (g.E == 32) TL_TILE(T, 32, 1024);              \
-  else if (g.E == 64 && nt == 512) TL_TILE(T, 64, 512);  \
-  else if (g.E == 64) TL_TILE(T, 64, 1024);              \
-  else return hipErrorInvalidValue;
+  const int E = g.E;
+  const int nt = tile_threads(E, mixed, ov);
+#define TL_TILE(T, EE, NT, OV) \
+  hipLaunchKernelGGL((k_tile<T, EE, NT, OV>), grid, dim3(NT), 0, stream, g, ea, mask, a)
   if (mixed) {
-    TL_TILE_ALL(float)
+    TL_TILE_OVERLAPS(TL_TILE, float)
   } else {
-    TL_TILE_ALL(double)
+    TL_TILE_OVERLAPS(TL_TILE, double)
   }
-#undef TL_TILE_ALL
 #undef TL_TILE
   return hipGetLastError();
 }
 
-hipError_t launch_tile_batch(bool mixed, int E, const BatchEntry* B, const int* tile_lat,
+hipError_t launch_tile_batch(bool mixed, int E, int ov, const BatchEntry* B, const int* tile_lat,
                              int ntiles, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 grid(ntiles);
-  const int nt = tile_threads(E, mixed);
-#define TL_TILEB(T, EE, NT) hipLaunchKernelGGL((k_tile_batch<T, EE, NT>), grid, dim3(NT), 0, stream, B, tile_lat)
-#define TL_TILEB_ALL(T)                                    \
-  if (E == 16) TL_TILEB(T, 16, 256);                       \
-  else if (E == 32 && nt == 256) TL_TILEB(T, 32, 256);     \
-  else if (E == 32 && nt == 512) TL_TILEB(T, 32, 512);     \
-  else if (E == 32) TL_TILEB(T, 32, 1024);                 \
-  else if (E == 64 && nt == 512) TL_TILEB(T, 64, 512);     \
-  else if (E == 64) TL_TILEB(T, 64, 1024);                 \
-  else return hipErrorInvalidValue;
+  const int nt = tile_threads(E, mixed, ov);
+#define TL_TILEB(T, EE, NT, OV) \
+  hipLaunchKernelGGL((k_tile_batch<T, EE, NT, OV>), grid, dim3(NT), 0, stream, B, tile_lat)
   if (mixed) {
-    TL_TILEB_ALL(float)
+    TL_TILE_OVERLAPS(TL_TILEB, float)
   } else {
-    TL_TILEB_ALL(double)
+    TL_TILE_OVERLAPS(TL_TILEB, double)
   }
-#undef TL_TILEB_ALL
 #undef TL_TILEB
   return hipGetLastError();
 }
+#undef TL_TILE_OVERLAPS
+#undef TL_TILE_SHAPES
 
 hipError_t launch_offdiag_batch(bool mixed, const BatchEntry* B, const int* set_lat, int nsets,
                                 hipStream_t stream) {

@@ -41,6 +41,7 @@ struct Opts {
   double rtol;
   int max_iters;
   int inner;
+  int overlap;           // relaxation region widened by this many nodes
   int coarse_iters;
   double coarse_rtol;
   int warm;
@@ -76,7 +77,7 @@ struct CoarseShape {
   int nwg, vec_lds, blk_lds;
 };
 CoarseShape coarse_shape(const Geo& g);
-void resolve_opts(const tl_opts* o, Opts* r);
+tl_status resolve_opts(const tl_opts* o, Opts* r);
 void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const double* f,
                          TileArgs* ta, OffArgs* oa, BlockArgs* ba, CoarseArgs* ca);
 tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f,

@@ -42,7 +42,7 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int32),
                 ("inner_iters", C.c_int32), ("coarse_iters", C.c_int32),
                 ("coarse_rtol", C.c_double), ("warm_start", C.c_int32),
-                ("trace", C.POINTER(Trace)), ("profile", C.c_int32)]
+                ("trace", C.POINTER(Trace)), ("profile", C.c_int32), ("overlap", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -206,7 +206,7 @@ def tl_lattice_create(nx, ny, ea=None, fixed=None, u_fixed=None, set_edge=0, str
 
 
 def make_opts(precision=TL_FP64, rtol=1e-8, max_iters=0, inner_iters=0, coarse_iters=0,
-              coarse_rtol=0.0, warm_start=False, trace=None, profile=False):
+              coarse_rtol=0.0, warm_start=False, trace=None, profile=False, overlap=0):
     o = Opts()
     o.precision = int(precision)
     o.rtol = float(rtol)
@@ -217,6 +217,7 @@ def make_opts(precision=TL_FP64, rtol=1e-8, max_iters=0, inner_iters=0, coarse_i
     o.warm_start = 1 if warm_start else 0
     o.trace = C.pointer(trace) if trace is not None else C.POINTER(Trace)()
     o.profile = 1 if profile else 0
+    o.overlap = int(overlap)
     return o
 
 

@@ -106,16 +106,19 @@ def _oracle_blocks(Kc, sets, s):
     return diag, off
 
 
-@pytest.mark.parametrize("nx,ny,E,ea,seed", [(64, 48, 16, "lognormal", 7), (45, 37, 16, "unit", 8),
-                                             (70, 66, 32, "lognormal", 9)])
-def test_one_iteration_matches_method_model(nx, ny, E, ea, seed):
+@pytest.mark.parametrize("nx,ny,E,ea,seed,ov", [
+    (64, 48, 16, "lognormal", 7, 0), (45, 37, 16, "unit", 8, 0), (70, 66, 32, "lognormal", 9, 0),
+    # relaxation on widened regions (section 2.2 end), ragged and clipped
+    (64, 48, 16, "lognormal", 7, 2), (45, 37, 16, "unit", 8, 4), (70, 66, 32, "lognormal", 9, 1),
+    (100, 72, 32, "lognormal", 10, 2), (70, 130, 64, "lognormal", 3, 2)])
+def test_one_iteration_matches_method_model(nx, ny, E, ea, seed, ov):
     """Every intermediate of one outer iteration (Eqs. 3, 6, 7, 8, 13) with
     the GPU's inner solves driven to convergence, against the oracle's exact
     step."""
     inst = make_instance(nx, ny, seed=seed, ea=ea)
     S = system_of(inst)
     sets = om.make_sets(nx, ny, E)
-    step = om.Method(S, sets).step(S.u_c.copy())
+    step = om.Method(S, sets, overlap=ov).step(S.u_c.copy())
     M, Q = sets.M, om.Q
     tr_t = dict(delta=torch.zeros((ny, nx, 2), dtype=torch.float64, device="cuda"),
                 kdiag=torch.zeros((M, Q, Q), dtype=torch.float64, device="cuda"),
@@ -127,8 +130,10 @@ def test_one_iteration_matches_method_model(nx, ny, E, ea, seed):
     lat = make_lattice(inst, E)
     f = dev(inst.f)
     u = torch.zeros_like(f)
+    R = E + 2 * ov
     info = tl.tl_solve(lat, f, u, check=False, precision=0, rtol=1e-300, max_iters=1,
-                       inner_iters=2 * E * E, coarse_iters=20000, coarse_rtol=1e-15, trace=trace)
+                       inner_iters=2 * R * R, coarse_iters=20000, coarse_rtol=1e-15, trace=trace,
+                       overlap=ov if ov > 0 else -1)
     torch.cuda.synchronize()
     assert info["status"] == tl.TL_E_NOCONV and info["iters"] == 1
     d_g = tr_t["delta"].cpu().numpy().reshape(-1)
@@ -143,6 +148,21 @@ def test_one_iteration_matches_method_model(nx, ny, E, ea, seed):
         assert np.abs(ko[s] - off).max() <= 1e-9 * nrm, s
     u1 = u.cpu().numpy().reshape(-1)
     assert np.linalg.norm(u1 - step.u_new) <= 1e-9 * np.linalg.norm(step.u_new)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("nx,ny,E,ea,seed,ov", [
+    (64, 64, 16, "unit", 0, 2), (100, 72, 32, "lognormal", 1, 2), (45, 37, 16, "lognormal", 2, 4),
+    (70, 130, 64, "lognormal", 3, 2), (17, 33, 16, "unit", 5, 1), (2, 2, 16, "unit", 4, 2)])
+def test_overlap_solve_matches_oracle(nx, ny, E, ea, seed, ov, precision):
+    inst = make_instance(nx, ny, seed=seed, ea=ea)
+    S = system_of(inst)
+    us = solve(S)
+    u, info, _ = gpu_solve(inst, E, precision, 1e-10, overlap=ov)
+    assert info["status"] == tl.TL_OK
+    assert max(info["rel_res_l1"], info["rel_res_l2"]) <= 1e-10
+    err = np.linalg.norm(u.reshape(-1) - us) / np.linalg.norm(us)
+    assert err <= 1e-8, (err, info)
 
 
 def test_energy_decreases_every_iteration():
@@ -231,3 +251,13 @@ def test_full_size_1024_fp64_certified():
     assert max(R1, R2) <= 1e-8
     fu, uKu = S.f @ uf, uf @ (S.K @ uf)
     assert abs(fu - uKu) <= 1e-6 * abs(fu)
+
+
+def test_unsupported_overlap_is_rejected():
+    inst = make_instance(40, 30, seed=13)
+    lat = make_lattice(inst, 16)
+    f = dev(inst.f)
+    u = torch.zeros_like(f)
+    for ov in (3, 5, 64):
+        info = tl.tl_solve(lat, f, u, check=False, overlap=ov)
+        assert info["status"] == tl.TL_E_INVAL
