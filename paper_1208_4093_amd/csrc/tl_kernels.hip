@@ -205,7 +205,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   // 2. residual r = f - K u (float64) and the per-node relaxation operator.
   float kk[NPT][6];
   double2 r[NPT];
-  T dxx[NPT], dxy[NPT], dyy[NPT], ixx[NPT], ixy[NPT], iyy[NPT];
+  T ixx[NPT], ixy[NPT], iyy[NPT];    // inverse of the node's 2x2 diagonal block
   bool act[NPT], own[NPT];
   double part[10];   // P1..P6, sum|r|, sum r^2, sum|f|, sum f^2
 #pragma unroll
@@ -239,7 +239,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   for (int k = 0; k < NPT; ++k) {
     const int n = t + k * NT, li = n % R, lj = n / R;
     r[k] = make_double2(0.0, 0.0);
-    dxx[k] = dxy[k] = dyy[k] = ixx[k] = ixy[k] = iyy[k] = (T)0;
+    ixx[k] = ixy[k] = iyy[k] = (T)0;
     if (!act[k]) continue;
     const int gi = ri0 + li, gj = rj0 + lj;
     const size_t p = pidx(g, gi, gj);
@@ -298,7 +298,6 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     const double kc = (double)kk[k][2] + kk[k][5];
     const double Dxx = ka + 0.25 * (kb + kc), Dyy = 0.75 * (kb + kc), Dxy = 0.5 * kS3 * (kb - kc);
     const double det = Dxx * Dyy - Dxy * Dxy;
-    dxx[k] = (T)Dxx; dxy[k] = (T)Dxy; dyy[k] = (T)Dyy;
     ixx[k] = (T)(Dyy / det); ixy[k] = (T)(-Dxy / det); iyy[k] = (T)(Dxx / det);
   }
   // workgroup reduction of the 10 partials and the max |r|
@@ -329,15 +328,17 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   //    Float32 form: r is scaled by 2^-e (e from max|r|) before rounding.
   const double rm = sfin[10];
   const double scl = (sizeof(T) == 4 && rm > 0.0 && isfinite(rm)) ? ldexp(1.0, -ilogb(rm)) : 1.0;
-  T2 x[NPT], rr[NPT], pp[NPT], zz[NPT], qq[NPT];
+  // Per node only x, r, p and K p stay in registers across the sweep's
+  // barriers; the diagonal block is rebuilt from the rod stiffnesses and
+  // z = B^-1 r is recomputed where it is needed (register pressure).
+  T2 x[NPT], rr[NPT], pp[NPT], qq[NPT];
   double rz_part = 0.0;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     x[k] = mk2<T>((T)0, (T)0);
     rr[k] = mk2<T>((T)(r[k].x * scl), (T)(r[k].y * scl));
-    zz[k] = mk2<T>(ixx[k] * rr[k].x + ixy[k] * rr[k].y, ixy[k] * rr[k].x + iyy[k] * rr[k].y);
-    pp[k] = zz[k];
-    rz_part += (double)(rr[k].x * zz[k].x + rr[k].y * zz[k].y);
+    pp[k] = mk2<T>(ixx[k] * rr[k].x + ixy[k] * rr[k].y, ixy[k] * rr[k].x + iyy[k] * rr[k].y);
+    rz_part += (double)(rr[k].x * pp[k].x + rr[k].y * pp[k].y);
   }
   double rz = block_sum<NW>(rz_part, sred[0]);
   for (int it = 0; it < A.inner_iters; ++it) {
@@ -355,8 +356,12 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       const int n = t + k * NT;
       const int c = (n / R + 1) * W + (n % R + 1);
       const T2 pa = pp[k];
-      T qx = dxx[k] * pa.x + dxy[k] * pa.y;
-      T qy = dxy[k] * pa.x + dyy[k] * pa.y;
+      const T ka = (T)kk[k][0] + (T)kk[k][3], kb = (T)kk[k][1] + (T)kk[k][4];
+      const T kc = (T)kk[k][2] + (T)kk[k][5];
+      const T Dxx = ka + (T)0.25 * (kb + kc), Dyy = (T)0.75 * (kb + kc);
+      const T Dxy = (T)(0.5 * kS3) * (kb - kc);
+      T qx = Dxx * pa.x + Dxy * pa.y;
+      T qy = Dxy * pa.x + Dyy * pa.y;
       T2 pb; T s;
       pb = sp[c + 1];     s = (T)kk[k][0] * pb.x;                                qx -= s;
       pb = sp[c - 1];     s = (T)kk[k][3] * pb.x;                                qx -= s;
@@ -374,16 +379,17 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     for (int k = 0; k < NPT; ++k) {
       x[k].x += alpha * pp[k].x;  x[k].y += alpha * pp[k].y;
       rr[k].x -= alpha * qq[k].x; rr[k].y -= alpha * qq[k].y;
-      zz[k] = mk2<T>(ixx[k] * rr[k].x + ixy[k] * rr[k].y, ixy[k] * rr[k].x + iyy[k] * rr[k].y);
-      rzn_part += (double)(rr[k].x * zz[k].x + rr[k].y * zz[k].y);
+      const T zx = ixx[k] * rr[k].x + ixy[k] * rr[k].y, zy = ixy[k] * rr[k].x + iyy[k] * rr[k].y;
+      rzn_part += (double)(rr[k].x * zx + rr[k].y * zy);
     }
     const double rzn = block_sum<NW>(rzn_part, sred[it & 1 ? 0 : 2]);
     const T beta = rz > 0.0 ? (T)(rzn / rz) : (T)0;
     rz = rzn;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      pp[k].x = zz[k].x + beta * pp[k].x;
-      pp[k].y = zz[k].y + beta * pp[k].y;
+      const T zx = ixx[k] * rr[k].x + ixy[k] * rr[k].y, zy = ixy[k] * rr[k].x + iyy[k] * rr[k].y;
+      pp[k].x = zx + beta * pp[k].x;
+      pp[k].y = zy + beta * pp[k].y;
     }
   }
 
@@ -887,7 +893,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   const bool warm = A.warm && iter > 0;
   for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = warm ? A.a[(size_t)w0 * Q + e] : 0.0;
   __syncthreads();
-  double red6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double red6[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int s = s0 + t; s < s1; s += COARSE_NT) {
 #pragma unroll
     for (int v = 0; v < NRM; ++v) red6[v] += A.nrm[(size_t)s * NRM + v];
@@ -907,6 +913,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     const double v = pinv_row(bi, s, s0, m, lown);
     pub_store(&A.pub0[r0 + e], v);    // B^+ P
     vz[e] = v;
+    red6[6] += lown[e] * v;           // P . B^+ P: the zero-start PCG residual
   }
   __syncthreads();
   for (int e = t; e < nrow; e += COARSE_NT) lown[e] = vn[e];
@@ -917,13 +924,14 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     pub_store(&A.pub1[r0 + e], v);    // B^+ y
     vq[e] = v;
   }
-  if (!grid_publish_wait<6>(red6, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
+  if (!grid_publish_wait<7>(red6, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
     return;
-  grid_collect<6>(A.red, slot, nwg, sv);
+  grid_collect<7>(A.red, slot, nwg, sv);
   slot ^= 1;
   __syncthreads();
 #pragma unroll
-  for (int v = 0; v < 6; ++v) red6[v] = sv[v];
+  for (int v = 0; v < 7; ++v) red6[v] = sv[v];
+  const double gamma_zero = red6[6];
   {
     const double R1 = red6[2] > 0.0 ? red6[0] / red6[2] : red6[0];
     const double R2 = red6[3] > 0.0 ? sqrt(red6[1] / red6[3]) : sqrt(red6[1]);
@@ -1015,7 +1023,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
       slot ^= 1;
       __syncthreads();
       const double gamma = sv[0], delta = sv[1];
-      if (it == 0) gamma0 = gamma;
+      if (it == 0) gamma0 = A.coarse_ref ? gamma_zero : gamma;
       if (it >= A.coarse_iters || !(gamma > 0.0) ||
           !(gamma > A.coarse_rtol * A.coarse_rtol * gamma0)) break;
       double alpha, beta;
@@ -1075,7 +1083,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     slot ^= 1;
     __syncthreads();
     const double gamma = sv[0], delta = sv[1];
-    if (it == 0) gamma0 = gamma;
+    if (it == 0) gamma0 = A.coarse_ref ? gamma_zero : gamma;
     if (it >= A.coarse_iters || !(gamma > 0.0) ||
         !(gamma > A.coarse_rtol * A.coarse_rtol * gamma0)) break;
     double alpha, beta;
