@@ -47,7 +47,12 @@ WORKLOADS = {
     "c1": dict(n=64, E=16, ea="unit", rtol=1e-10, headline="fp64",
                desc="triangle lattice 64x64 nodes (8,192 DOF), EA=1, L=1, nodes i=0 clamped, "
                     "loads N(0,1) seed 0, sets 16x16 nodes, stop at rel. residual 1e-10"),
+    # traffic: HBM bytes per k_tile launch of the headline form from the
+    # FETCH_SIZE / WRITE_SIZE counter runs in profiles/counters_k_tile_c2_1024.md
+    # (FETCH x 2.0, WRITE x 1.0, calibrated on copy kernels); None when the
+    # kernel has changed since the counters were taken.
     "c2": dict(n=1024, E=32, ea="unit", rtol=1e-8, headline="fp64",
+               traffic_bytes=(33067.7 * 2.0 + 33088.0) * 1024,
                desc="triangle lattice 1024x1024 nodes (2,097,152 DOF), EA=1, L=1, left edge "
                     "clamped, loads N(0,1) seed 0, sets 32x32 nodes, stop at rel. residual 1e-8"),
     "c3": dict(n=16384, E=64, ea="lognormal", rtol=1e-10, headline="mixed",
@@ -226,7 +231,9 @@ def run_single(args, wl):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": head["tile_gbs"] / HBM_PEAK_GBS,
-        "traffic": wl.get("traffic"),
+        "traffic": (wl["traffic_bytes"] / (tile_ms * 1e-3) / 1e9
+                    if wl.get("traffic_bytes") else None),
+        "traffic_bytes_per_launch": wl.get("traffic_bytes"),
         "avg_launch_us": 1000.0 * tile_ms,
         "algorithmic_bytes_per_launch": head["tile_bytes_per_launch"],
         "time_share": head["kernel_share"]["tile"],
