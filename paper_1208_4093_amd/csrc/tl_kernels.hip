@@ -66,6 +66,42 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Wave sums of V values at once (V a power of two, at most 64) with about V
+// shuffles instead of 6V: at each halving step a lane keeps half of the
+// values it still holds and adds the partner's copy of that half, so after
+// the six steps lane l holds the wave total of value l >> (6 - log2 V).
+// Lanes that end with the same value hold the same bits.
+template <int V>
+__device__ __forceinline__ double wave_sums(double (&v)[V]) {
+  static_assert(V >= 1 && V <= 64 && (V & (V - 1)) == 0, "V must be a power of two <= 64");
+  const int lane = threadIdx.x & 63;
+  int h = V;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    if (h > 1) {
+      h >>= 1;
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int j = 0; j < V / 2; ++j) {
+        if (j < h) {
+          const double send = up ? v[j] : v[j + h];
+          const double keep = up ? v[j + h] : v[j];
+          v[j] = keep + __shfl_xor(send, o, 64);
+        }
+      }
+    } else {
+      v[0] += __shfl_xor(v[0], o, 64);
+    }
+  }
+  return v[0];
+}
+
+template <int V>
+__device__ __forceinline__ int wave_sums_index() {
+  constexpr int lg = V >= 64 ? 6 : V >= 32 ? 5 : V >= 16 ? 4 : V >= 8 ? 3 : V >= 4 ? 2 : V >= 2 ? 1 : 0;
+  return (threadIdx.x & 63) >> (6 - lg);
+}
+
 // Workgroup sum; every thread gets the same (bitwise) value.  `slot` holds
 // one entry per wave and must not be reused before the next barrier.
 template <int NW, typename T>
@@ -131,6 +167,11 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   __shared__ double sred[3][NW];
   __shared__ double sacc[NW][KROW + 3];
   __shared__ double sfin[11];
+  // With 64 x 64 sets (four or more nodes per thread) the region's float64
+  // residual waits in LDS, not in registers, for the relaxation's start and
+  // the upper-level rows, when it fits beside the node buffer.
+  constexpr bool kResidLds = E >= 64 && (W * W + R * R) * 16 + 8192 <= 160 * 1024;
+  __shared__ double2 sres[kResidLds ? R * R : 1];
   T2* sp = reinterpret_cast<T2*>(su);
 
   if (A.ctrl->done) return;
@@ -213,8 +254,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   double rmax = 0.0;
   double2 fl[NPT];
   // all of the thread's loads first (one memory latency), then the arithmetic
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
+  auto load_node = [&](const int k) {
     const int n = t + k * NT, li = n % R, lj = n / R;
     act[k] = false;
     own[k] = false;
@@ -234,9 +274,20 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       kk[k][5] = ea[2 * plane + p - g.pitch + 1];
       fl[k] = A.f[(size_t)gj * g.nx + gi];
     }
+  };
+  // With 64 x 64 sets the loads of all of a thread's nodes do not fit in
+  // registers beside the arithmetic: each node's loads then precede its own
+  // arithmetic, fenced so the scheduler keeps that order.
+  if constexpr (!kResidLds) {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) load_node(k);
   }
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
+    if constexpr (kResidLds) {
+      __builtin_amdgcn_sched_barrier(0);
+      load_node(k);
+    }
     const int n = t + k * NT, li = n % R, lj = n / R;
     r[k] = make_double2(0.0, 0.0);
     ixx[k] = ixy[k] = iyy[k] = (T)0;
@@ -277,6 +328,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       }
     }
     r[k] = make_double2(rx, ry);
+    if constexpr (kResidLds) sres[t + k * NT] = r[k];
     rmax = fmax(rmax, fmax(fabs(rx), fabs(ry)));
     if (own[k]) {
       double xi, eta;
@@ -302,14 +354,25 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   }
   // workgroup reduction of the 10 partials and the max |r|
   {
+    // (the many-value wave sums pay off below 64 x 64 sets; at 64 x 64 the
+    //  registers they hold spill)
+    if constexpr (NPT <= 3) {
+      double p16[16];
 #pragma unroll
-    for (int v = 0; v < 10; ++v) part[v] = wave_sum(part[v]);
-    rmax = wave_max(rmax);
-    if ((t & 63) == 0) {
+      for (int v = 0; v < 16; ++v) p16[v] = v < 10 ? part[v] : 0.0;
+      const double ps = wave_sums<16>(p16);
+      const int v = wave_sums_index<16>();
+      if ((t & 3) == 0 && v < 10) sacc[t >> 6][v] = ps;
+    } else {
 #pragma unroll
-      for (int v = 0; v < 10; ++v) sacc[t >> 6][v] = part[v];
-      sacc[t >> 6][10] = rmax;
+      for (int v = 0; v < 10; ++v) part[v] = wave_sum(part[v]);
+      if ((t & 63) == 0) {
+#pragma unroll
+        for (int v = 0; v < 10; ++v) sacc[t >> 6][v] = part[v];
+      }
     }
+    rmax = wave_max(rmax);
+    if ((t & 63) == 0) sacc[t >> 6][10] = rmax;
     __syncthreads();   // also: every read of su as u is done
     if (t < 11) {
       double s = 0.0;
@@ -336,7 +399,8 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     x[k] = mk2<T>((T)0, (T)0);
-    rr[k] = mk2<T>((T)(r[k].x * scl), (T)(r[k].y * scl));
+    const double2 rk = kResidLds ? (act[k] ? sres[t + k * NT] : make_double2(0.0, 0.0)) : r[k];
+    rr[k] = mk2<T>((T)(rk.x * scl), (T)(rk.y * scl));
     pp[k] = mk2<T>(ixx[k] * rr[k].x + ixy[k] * rr[k].y, ixy[k] * rr[k].x + iyy[k] * rr[k].y);
     rz_part += (double)(rr[k].x * pp[k].x + rr[k].y * pp[k].y);
   }
@@ -460,16 +524,26 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       acc[q * 9 + 7] += xi * dw;
       acc[q * 9 + 8] += eta * dw;
     }
-    const double dr = dax * r[k].x + day * r[k].y;
+    const double2 rk = kResidLds ? sres[n] : r[k];
+    const double dr = dax * rk.x + day * rk.y;
     acc[KROW + 0] += dr;
     acc[KROW + 1] += xi * dr;
     acc[KROW + 2] += eta * dr;
   }
+  if constexpr (NPT <= 3) {
+    double a32[32];
 #pragma unroll
-  for (int v = 0; v < KROW + 3; ++v) acc[v] = wave_sum(acc[v]);
-  if ((t & 63) == 0) {
+    for (int v = 0; v < 32; ++v) a32[v] = v < KROW + 3 ? acc[v] : 0.0;
+    const double as = wave_sums<32>(a32);
+    const int v = wave_sums_index<32>();
+    if ((t & 1) == 0 && v < KROW + 3) sacc[t >> 6][v] = as;
+  } else {
 #pragma unroll
-    for (int v = 0; v < KROW + 3; ++v) sacc[t >> 6][v] = acc[v];
+    for (int v = 0; v < KROW + 3; ++v) acc[v] = wave_sum(acc[v]);
+    if ((t & 63) == 0) {
+#pragma unroll
+      for (int v = 0; v < KROW + 3; ++v) sacc[t >> 6][v] = acc[v];
+    }
   }
   __syncthreads();
   if (t < KROW + 3) {
