@@ -772,46 +772,48 @@ __device__ __forceinline__ double pub_load(const double* p) {
 }
 
 // Grid-wide sum of up to REDW values, which is also the grid barrier.
-// Workgroup w publishes its partials in slot `slot`, waits for its own
-// stores, then raises flags[w] to `gen`; every workgroup waits until all
-// flags have reached `gen` and adds the partials in workgroup order, so all
-// threads of all workgroups get the same bits.  No counter is shared, so
-// arrivals do not serialise on one address.  A workgroup can run at most one
-// sum ahead of the slowest, hence two slots and the wrap-safe ">= gen" test.
-// Bounded: after spin_limit polls the error flag is raised and every later
-// sum returns false at once, so the grid always drains.
-// Publish this workgroup's partials of a grid sum (slot `slot`) and wait
-// until every workgroup has published (its flag reached `gen`).  Workgroup w
-// writes its partials, waits for its own stores, then raises flags[w]; no
-// counter is shared, so arrivals do not serialise on one address.  A
-// workgroup can run at most one sum ahead of the slowest, hence two slots and
-// the wrap-safe ">= gen" test.  Bounded: after spin_limit polls the error
-// flag is raised and every later call returns false at once, so the grid
-// always drains.  With one workgroup the partials are left in sv and no
-// memory round trip is made.
+// Workgroup w publishes its partials in slot `slot`, waits for all of its
+// stores (the partials and any values published before the call), then
+// raises flags[w] to `gen`; every workgroup waits until all flags have
+// reached `gen` and adds the partials in workgroup order, so all threads of
+// all workgroups get the same bits.  No counter is shared, so arrivals do not
+// serialise on one address.  A workgroup can run at most one sum ahead of the
+// slowest, hence two slots and the wrap-safe ">= gen" test.  Bounded: after
+// spin_limit polls the error flag is raised and every later call returns
+// false at once, so the grid always drains.  With one workgroup the partials
+// are left in sv and no memory round trip is made.
 template <int NV>
 __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* flags,
                                   unsigned gen, int slot, Ctrl* c, int wid, int nwg,
                                   unsigned spin, double* sslot, double* sv) {
   __shared__ int ok;
+  __shared__ double wsum[NV][COARSE_NT / 64];
   static_assert(NV <= REDW, "too many values for one grid sum");
-  __builtin_amdgcn_s_waitcnt(0);   // every wave's published stores have completed
+  // the workgroup's sums of the NV values: one barrier for all of them
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    const double bs = block_sum<COARSE_NT / 64>(v[k], sslot);
-    if (threadIdx.x == 0) {
-      if (nwg == 1) sv[k] = bs;
-      else pub_store(&red[((size_t)slot * COARSE_MAX_WG + wid) * REDW + k], bs);
-    }
-    __syncthreads();
+    const double ws = wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) wsum[k][threadIdx.x >> 6] = ws;
   }
-  if (nwg == 1) return true;
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double bs = 0.0;
+#pragma unroll
+    for (int w = 0; w < COARSE_NT / 64; ++w) bs += wsum[threadIdx.x][w];
+    if (nwg == 1) sv[threadIdx.x] = bs;
+    else pub_store(&red[((size_t)slot * COARSE_MAX_WG + wid) * REDW + threadIdx.x], bs);
+  }
+  if (nwg == 1) {
+    __syncthreads();
+    return true;
+  }
+  // one wait covers every store of this workgroup: published values and partials
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
   if (threadIdx.x < 64) {
     int good = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-    if (threadIdx.x == 0 && good) {
-      __builtin_amdgcn_s_waitcnt(0);
+    if (threadIdx.x == 0 && good)
       __hip_atomic_store(&flags[wid], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     unsigned n = 0;
     while (good) {
       bool mine = true;
@@ -828,24 +830,64 @@ __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* 
     if (threadIdx.x == 0) ok = good;
   }
   __syncthreads();
+  (void)sslot;
   return ok != 0;
 }
 
-// Add the published partials (after grid_publish_wait) into sv: one wave,
-// lane l takes workgroups l, l + 64, ... in order, then a butterfly; the same
-// tree in every workgroup, so every workgroup gets the same bits.  Only
-// thread 0 writes sv; the caller synchronises before reading it.
+// After a grid sum: add the published partials into sv (one wave; lane l
+// takes workgroups l, l + 64, ... in order, then a butterfly, the same tree
+// in every workgroup, so every workgroup gets the same bits) and copy the
+// neighbours' published window values into LDS.  All loads are issued
+// before any is used, so the two take one memory round trip together.
+// Only thread 0 writes sv; the caller synchronises before reading it or dst.
+template <int NV>
+__device__ void grid_collect_window(const double* red, int slot, int nwg, double* sv,
+                                    double* dst, const double* src, int n) {
+  constexpr int PW = COARSE_MAX_WG / 64;
+  constexpr int WB = 8;
+  const int t = threadIdx.x;
+  double pv[NV][PW];
+  if (nwg > 1 && t < 64) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int j = 0; j < PW; ++j) {
+        const int w = t + 64 * j;
+        pv[k][j] = w < nwg ? pub_load(&red[((size_t)slot * COARSE_MAX_WG + w) * REDW + k]) : 0.0;
+      }
+  }
+  if (nwg > 1 && src) {
+    for (int base = 0; base < n; base += WB * COARSE_NT) {
+      double wv[WB];
+#pragma unroll
+      for (int b = 0; b < WB; ++b) {
+        const int e = base + t + b * COARSE_NT;
+        wv[b] = e < n ? pub_load(&src[e]) : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < WB; ++b) {
+        const int e = base + t + b * COARSE_NT;
+        if (e < n) dst[e] = wv[b];
+      }
+    }
+  }
+  if (nwg > 1 && t < 64) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < PW; ++j)
+        if (t + 64 * j < nwg) s += pv[k][j];
+      s = wave_sum(s);
+      if (t == 0) sv[k] = s;
+    }
+  }
+}
+
+// The partial sums alone (no window).
 template <int NV>
 __device__ void grid_collect(const double* red, int slot, int nwg, double* sv) {
-  if (nwg == 1 || threadIdx.x >= 64) return;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-    for (int w = threadIdx.x; w < nwg; w += 64)
-      s += pub_load(&red[((size_t)slot * COARSE_MAX_WG + w) * REDW + k]);
-    s = wave_sum(s);
-    if (threadIdx.x == 0) sv[k] = s;
-  }
+  grid_collect_window<NV>(red, slot, nwg, sv, nullptr, nullptr, 0);
 }
 
 // (K_a v) for one row of the workgroup's own sets, v from the LDS window that
@@ -1091,9 +1133,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
       }
       if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
         return;
-      grid_collect<2>(A.red, slot, nwg, sv);
-      if (nwg > 1)
-        for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = pub_load(&mpub[(size_t)w0 * Q + e]);
+      grid_collect_window<2>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q);
       slot ^= 1;
       __syncthreads();
       const double gamma = sv[0], delta = sv[1];
@@ -1151,9 +1191,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
       return;
     // one round trip: the partial sums and the neighbours' m together
-    grid_collect<2>(A.red, slot, nwg, sv);
-    if (nwg > 1)
-      for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = pub_load(&mpub[(size_t)w0 * Q + e]);
+    grid_collect_window<2>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q);
     slot ^= 1;
     __syncthreads();
     const double gamma = sv[0], delta = sv[1];
