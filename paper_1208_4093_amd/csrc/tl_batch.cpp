@@ -68,7 +68,8 @@ struct Job {
 // alone, so its grid-sum order, and with it every rounding, is the same alone
 // and in any batch.  All workgroups of the launch must be co-resident (each
 // lattice's grid sums wait on its own workgroups), so the plan picks an LDS
-// size class (76 KB: two workgroups per CU; else 150 KB: one) that every
+// size class (64 KB: two workgroups per CU beside the static arrays; else
+// 144 KB: one) that every
 // lattice's unstaged slice fits, checks the total against the co-resident
 // capacity at that class, and enables LDS staging per lattice where it still
 // fits the class.  Returns false when the lattices cannot all be co-resident.
@@ -83,7 +84,7 @@ bool plan_coarse(const std::vector<const Geo*>& gs, std::vector<int>* nw_out,
     nw[b] = shape[b].nwg;
     used += nw[b];
   }
-  static const size_t classes[2] = {76 * 1024, 150 * 1024};
+  static const size_t classes[2] = {64 * 1024, COARSE_DYN_LDS_MAX};
   for (size_t cap : classes) {
     bool ok = true;
     for (int b = 0; b < n && ok; ++b) ok = coarse_lds_bytes(*gs[b], nw[b], 0, 0) <= cap;
@@ -250,9 +251,12 @@ tl_status alloc_and_start(Job* j, hipStream_t st) {
     tl_status s = j->w->alloc(j->L->g, j->o.mixed, j->o.max_iters + 1);
     if (s != TL_OK) return s;
   }
-  return hip_status(launch_init_state(j->L->g, j->L->mask, j->L->ufix, (const double2*)j->u,
-                                      j->o.warm, j->w->u[0], j->w->u[1], j->w->d[0], j->w->d[1],
-                                      j->o.mixed, j->w->a, j->w->flags, j->w->ctrl, st));
+  tl_status s = hip_status(launch_init_state(j->L->g, j->L->mask, j->L->ufix, (const double2*)j->u,
+                                             j->o.warm, j->w->u[0], j->w->u[1], j->w->d[0],
+                                             j->w->d[1], j->o.mixed, j->w->a, j->w->flags,
+                                             j->w->ctrl, st));
+  if (s == TL_OK) s = ensure_coarse_space(j->L, j->w, j->o, j->f, st);
+  return s;
 }
 
 // Retire a job whose control block says it stopped: copy out u and certify.

@@ -67,7 +67,7 @@ size_t padded_nodes(const Geo& g) { return (size_t)(g.ny + 2) * g.pitch; }
 size_t work_bytes(const Geo& g, bool mixed, int hist_cap) {
   const size_t np = padded_nodes(g), M = g.M;
   size_t b = 2 * np * sizeof(double2) + 2 * np * (mixed ? sizeof(float2) : sizeof(double2));
-  b += M * (Q + KROW + Q + NRM + NDIR * Q * Q + 2 * Q * Q + 10 * Q) * sizeof(double);
+  b += M * (Q + KROW + Q + NRM + NDIR * Q * Q + 2 * Q * Q + 11 * Q) * sizeof(double);
   b += 2 * COARSE_MAX_WG * REDW * sizeof(double) + (size_t)hist_cap * sizeof(double);
   b += COARSE_MAX_WG * sizeof(unsigned);
   b += sizeof(Ctrl);
@@ -106,7 +106,7 @@ tl_status Work::alloc(const Geo& g_, bool mixed_, int hist_cap_) {
   TL_TRY(get(M * NDIR * Q * Q * sizeof(double), &p)); off = (double*)p;
   TL_TRY(get(M * Q * Q * sizeof(double), &p)); bdiag = (double*)p;
   TL_TRY(get(M * Q * Q * sizeof(double), &p)); binv = (double*)p;
-  double** vecs[] = {&cr, &cu, &cw, &cz, &cq, &cs, &cp, &cn, &pub0, &pub1};
+  double** vecs[] = {&cr, &cu, &cw, &cz, &cq, &cs, &cp, &cn, &pub0, &pub1, &pub2};
   for (double** v : vecs) {
     TL_TRY(get(M * Q * sizeof(double), &p));
     *v = (double*)p;
@@ -123,7 +123,7 @@ tl_status Work::alloc(const Geo& g_, bool mixed_, int hist_cap_) {
 // Launch shape of the upper-level kernel: about `per` sets per workgroup, at
 // most one workgroup per CU and few enough that each one's LDS windows fit;
 // the own vectors and blocks go to LDS when there is room.
-constexpr size_t kCoarseLdsCap = 150 * 1024;
+constexpr size_t kCoarseLdsCap = COARSE_DYN_LDS_MAX;
 
 CoarseShape coarse_shape(const Geo& g) {
   const int per = std::max(1, env_int("TL_COARSE_SETS_PER_WG", 16));
@@ -204,6 +204,7 @@ void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const doub
   ca->cn = w->cn;
   ca->pub0 = w->pub0;
   ca->pub1 = w->pub1;
+  ca->pub2 = w->pub2;
   ca->red = w->red;
   ca->flags = w->flags;
   ca->hist = (o.trace && o.trace->residual_history) ? o.trace->residual_history : w->hist;
@@ -217,11 +218,38 @@ void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const doub
   ca->coarse_rtol = o.coarse_rtol;
   ca->rtol = o.rtol;
   ca->warm = env_int("TL_COARSE_WARM", 1);
+  ca->coarse_ref = env_int("TL_COARSE_REF", 0);
   ca->spin_limit = 1u << 22;
   const CoarseShape cs = coarse_shape(L->g);
   ca->nwg = cs.nwg;
   ca->vec_lds = cs.vec_lds;
   ca->blk_lds = cs.blk_lds;
+  // the coarse space, when built and laid out for this workgroup count
+  const bool two = L->agg_ready && L->agg_nwg == cs.nwg && env_int("TL_COARSE_2LEVEL", 1) != 0;
+  ca->agg_inv = two ? L->agg_inv : nullptr;
+  ca->agg_xy = two ? L->agg_xy : nullptr;
+  ca->naggr = two ? L->naggr : 0;
+  ca->agg_sets = two ? L->agg_sets : 1;
+  ca->agg_g = two ? L->agg_g : 1;
+}
+
+tl_status ensure_coarse_space(tl_lattice* L, Work* w, const Opts& o, const double* f,
+                              hipStream_t st) {
+  if (L->agg_ready || env_int("TL_COARSE_2LEVEL", 1) == 0) return TL_OK;
+  std::lock_guard<std::mutex> lock(L->agg_mu);
+  if (L->agg_ready) return TL_OK;
+  // the boundary blocks of the just-initialised state (relaxation increments
+  // zero) carry the constant mode 1-6 corners that the coarse space needs
+  TileArgs ta;
+  OffArgs oa;
+  BlockArgs ba;
+  CoarseArgs ca;
+  make_iteration_args(L, w, o, f, &ta, &oa, &ba, &ca);
+  TL_TRY(launch_offdiag(o.mixed, L->g, L->ea, L->mask, oa, st));
+  TL_TRY(launch_agg_setup(L->g, L->g1, w->off, L->agg_xy, L->agg_sets, L->naggr, L->agg_inv, st));
+  TL_TRY(hipStreamSynchronize(st));
+  L->agg_ready = true;
+  return TL_OK;
 }
 
 // Enqueue one outer iteration of one solve (ev: optional 4 timing events).
@@ -263,6 +291,10 @@ tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, doub
   TL_TRY(hipEventCreate(&e1));
   TL_TRY(launch_init_state(L->g, L->mask, L->ufix, (const double2*)u, o.warm, w->u[0], w->u[1],
                            w->d[0], w->d[1], o.mixed, w->a, w->flags, w->ctrl, st));
+  {
+    const tl_status cs = ensure_coarse_space(L, w, o, f, st);
+    if (cs != TL_OK) return cs;
+  }
   TL_TRY(hipEventRecord(e0, st));
   int k = 0, chunk = 4;
   tl_status st_run = TL_OK;
@@ -482,6 +514,41 @@ tl_status tl_lattice_create(const tl_lattice_desc* desc, void* hip_stream, tl_la
     e = hipMemcpy(L->ufix, desc->u_fixed, nn * sizeof(double2),
                   desc->ptrs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(from_hip(e));
+  }
+  // Coarse space of the upper-level preconditioner: aggregates of whole
+  // upper-level workgroups (at most AGG_MAX of them), centroids on the host.
+  {
+    const CoarseShape cs = coarse_shape(L->g);
+    const int M = L->g.M;
+    const AggLayout al = agg_layout(M, L->g.mx, cs.nwg);
+    L->agg_nwg = cs.nwg;
+    L->agg_g = al.g;
+    L->agg_sets = al.sets;
+    L->naggr = al.naggr;
+    std::vector<double> xy(2 * (size_t)L->naggr, 0.0);
+    std::vector<int> cnt(L->naggr, 0);
+    for (int sidx = 0; sidx < M; ++sidx) {
+      const int I = sidx % L->g.mx, J = sidx / L->g.mx, E = L->g.E;
+      const int i0 = I * E, j0 = J * E;
+      const int tw = std::min(E, L->g.nx - i0), th = std::min(E, L->g.ny - j0);
+      const double ic = i0 + 0.5 * (tw - 1), jc = j0 + 0.5 * (th - 1);
+      const int a = sidx / L->agg_sets;
+      xy[2 * a] += ic + 0.5 * jc;
+      xy[2 * a + 1] += jc * 0.86602540378443864676;
+      ++cnt[a];
+    }
+    for (int a = 0; a < L->naggr; ++a) {
+      xy[2 * a] /= cnt[a];
+      xy[2 * a + 1] /= cnt[a];
+    }
+    const size_t n = 6 * (size_t)L->naggr;
+    if ((e = dalloc(&p, n * n * sizeof(double))) != hipSuccess) return fail(from_hip(e));
+    L->agg_inv = (double*)p;
+    if ((e = dalloc(&p, xy.size() * sizeof(double))) != hipSuccess) return fail(from_hip(e));
+    L->agg_xy = (double*)p;
+    if ((e = hipMemcpy(L->agg_xy, xy.data(), xy.size() * sizeof(double), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return fail(from_hip(e));
   }
   e = launch_group1(L->g, L->ea, L->mask, L->g1, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);

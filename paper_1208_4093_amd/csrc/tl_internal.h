@@ -29,11 +29,35 @@ constexpr int NRM = 4;          // sum|r|, sum r^2, sum|f|, sum f^2 (free DOFs)
 constexpr int TILE_OUT = KROW + Q + NRM;
 constexpr int COARSE_NT = 256;  // threads per upper-level workgroup
 constexpr int COARSE_MAX_WG = 256;
-constexpr int REDW = 8;         // values per workgroup and slot of a grid sum
+constexpr int REDW = 24;        // values per workgroup and slot of a grid sum
+constexpr int AGG_MAX = 32;     // aggregates of the upper-level coarse space (at most)
+constexpr int AGG_GMAX = 8;     // workgroups per aggregate (at most: COARSE_MAX_WG / AGG_MAX)
+// Dynamic LDS of one upper-level workgroup, at most: the 160 KB of a CU less
+// the kernel's static arrays (grid-sum and coarse-space scratch, under 16 KB).
+constexpr size_t COARSE_DYN_LDS_MAX = 144 * 1024;
 constexpr int LPAD = 32;        // left padding (elements) of node arrays: interior
                                 // rows start on a 128-byte boundary for every type
 
 // Set-grid neighbour offsets (dI, dJ); direction d and d + 3 are opposite.
+// Aggregates of the upper-level coarse space for a lattice of M sets (mx per
+// row) whose upper level runs on nwg workgroups: runs of `g` whole workgroups
+// (`sets` sets), `naggr` of them, and at most `nwa_max` of them meet one
+// workgroup's window of neighbour sets.
+struct AggLayout {
+  int g, sets, naggr, nwa_max;
+};
+__host__ __device__ inline AggLayout agg_layout(int M, int mx, int nwg) {
+  AggLayout a;
+  const int spw = (M + nwg - 1) / nwg;
+  a.g = (nwg + AGG_MAX - 1) / AGG_MAX;
+  a.sets = spw * a.g;
+  a.naggr = (M + a.sets - 1) / a.sets;
+  const int win = M < spw + 2 * mx + 2 ? M : spw + 2 * mx + 2;
+  const int span = win / a.sets + 2;
+  a.nwa_max = a.naggr < span ? a.naggr : span;
+  return a;
+}
+
 __host__ __device__ constexpr int nb_di(int d) { return d == 0 ? 1 : d == 2 ? -1 : d == 3 ? -1 : d == 5 ? 1 : 0; }
 __host__ __device__ constexpr int nb_dj(int d) { return d == 1 ? 1 : d == 2 ? 1 : d == 4 ? -1 : d == 5 ? -1 : 0; }
 
@@ -90,8 +114,14 @@ struct CoarseArgs {
   double* cs;
   double* cp;
   double* cn;
-  double* pub0;          // [9M] published vectors read by neighbouring sets (ping)
-  double* pub1;          // [9M] (pong)
+  // Published vectors read by neighbouring sets: the start publishes B^+ P in
+  // pub0 and B^+ y in pub1; PCG iteration it publishes m in pub2 (it even)
+  // or pub0 (it odd), so no workgroup overwrites a vector that a slower one
+  // may still be reading (the start's pair stays untouched until every
+  // workgroup has passed the first iteration's grid sum).
+  double* pub0;          // [9M]
+  double* pub1;          // [9M]
+  double* pub2;          // [9M]
   double* red;           // [2][COARSE_MAX_WG][REDW] reduction slots
   unsigned* flags;       // [COARSE_MAX_WG] arrival generations of the grid sums
   double* hist;          // [max_iters + 1] max(R1, R2) per outer iteration (may be null)
@@ -106,6 +136,16 @@ struct CoarseArgs {
   double rtol;
   int nwg;
   int warm;              // warm-start the upper-level PCG from the previous coefficients
+  int coarse_ref;        // PCG tolerance relative to 1: the zero-start residual, 0: the initial one
+  // Coarse space of the PCG preconditioner (naggr = 0: block-Jacobi alone):
+  // aggregates of agg_sets consecutive sets (agg_g workgroups each), six
+  // affine fields per aggregate, agg_inv the pseudo-inverse of their
+  // upper-level matrix ([6 naggr][6 naggr]), agg_xy their centroids.
+  const double* agg_inv;
+  const double* agg_xy;
+  int naggr;
+  int agg_sets;
+  int agg_g;
   int vec_lds;           // 1: own PCG vectors in LDS
   int blk_lds;           // 1: own blocks staged in LDS
   unsigned spin_limit;
@@ -150,6 +190,12 @@ hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8
 hipError_t launch_blockinv(const Geo& g, const BlockArgs& a, hipStream_t stream);
 hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream);
 size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds);
+// Coarse space of the upper-level preconditioner: A0 = P0^T K_a P0 from the
+// constant blocks (g1 and the mode 1-6 corners of off), then its
+// pseudo-inverse in place.
+hipError_t launch_agg_setup(const Geo& g, const double* g1, const double* off,
+                            const double* agg_xy, int agg_sets, int naggr, double* A0,
+                            hipStream_t stream);
 // Fused launches over a batch (entries and lookup tables in device memory).
 hipError_t launch_tile_batch(bool mixed, int E, int ov, const BatchEntry* B, const int* tile_lat,
                              int ntiles, hipStream_t stream);

@@ -836,15 +836,21 @@ __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* 
 
 // After a grid sum: add the published partials into sv (one wave; lane l
 // takes workgroups l, l + 64, ... in order, then a butterfly, the same tree
-// in every workgroup, so every workgroup gets the same bits) and copy the
-// neighbours' published window values into LDS.  All loads are issued
-// before any is used, so the two take one memory round trip together.
-// Only thread 0 writes sv; the caller synchronises before reading it or dst.
-template <int NV>
+// in every workgroup, so every workgroup gets the same bits), copy the
+// neighbours' published window values into LDS, and (agg_nvec > 0) gather
+// the coarse-space restrictions: for each of agg_nvec vectors, entry
+// (aggregate a, mode k) is the sum, in workgroup order, of partial
+// agg_k0 + 6 v + k of the agg_g workgroups of aggregate a.  All loads are
+// issued before any is used, so they take one memory round trip together.
+// Only the collecting threads write sv / s_c; the caller synchronises.
+template <int NV, int NVEC = 1>
 __device__ void grid_collect_window(const double* red, int slot, int nwg, double* sv,
-                                    double* dst, const double* src, int n) {
+                                    double* dst, const double* src, int n,
+                                    int agg_k0 = 0, int agg_nvec = 0, int agg_g = 1,
+                                    int naggr = 0, double* s_c = nullptr) {
   constexpr int PW = COARSE_MAX_WG / 64;
-  constexpr int WB = 8;
+  constexpr int WB = 4;
+  constexpr int CB = (NVEC * 6 * AGG_MAX + COARSE_NT - 1) / COARSE_NT;
   const int t = threadIdx.x;
   double pv[NV][PW];
   if (nwg > 1 && t < 64) {
@@ -855,6 +861,23 @@ __device__ void grid_collect_window(const double* red, int slot, int nwg, double
         const int w = t + 64 * j;
         pv[k][j] = w < nwg ? pub_load(&red[((size_t)slot * COARSE_MAX_WG + w) * REDW + k]) : 0.0;
       }
+  }
+  // coarse-space restrictions: entries t, t + NT of the agg_nvec * 6 * naggr
+  double cv[CB][AGG_GMAX];
+  const int ctot = agg_nvec * 6 * naggr;
+#pragma unroll
+  for (int b = 0; b < CB; ++b) {
+    const int e = t + b * COARSE_NT;
+    const int v = e / (6 * max(naggr, 1)), idx = e - v * 6 * max(naggr, 1);
+    const int ag = idx / 6, k = idx - 6 * ag;
+#pragma unroll
+    for (int j = 0; j < AGG_GMAX; ++j) {
+      const int w = ag * agg_g + j;
+      cv[b][j] = (e < ctot && j < agg_g && w < nwg)
+                     ? (nwg > 1 ? pub_load(&red[((size_t)slot * COARSE_MAX_WG + w) * REDW + agg_k0 + 6 * v + k])
+                                : 0.0)
+                     : 0.0;
+    }
   }
   if (nwg > 1 && src) {
     for (int base = 0; base < n; base += WB * COARSE_NT) {
@@ -874,12 +897,25 @@ __device__ void grid_collect_window(const double* red, int slot, int nwg, double
   if (nwg > 1 && t < 64) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
+      double sum = 0.0;
 #pragma unroll
       for (int j = 0; j < PW; ++j)
-        if (t + 64 * j < nwg) s += pv[k][j];
-      s = wave_sum(s);
-      if (t == 0) sv[k] = s;
+        if (t + 64 * j < nwg) sum += pv[k][j];
+      sum = wave_sum(sum);
+      if (t == 0) sv[k] = sum;
+    }
+  }
+  if (nwg > 1) {
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int e = t + b * COARSE_NT;
+      if (e < ctot) {
+        double sum = 0.0;
+#pragma unroll
+        for (int j = 0; j < AGG_GMAX; ++j) sum += cv[b][j];
+        const int v = e / (6 * naggr);
+        s_c[v * 6 * AGG_MAX + (e - v * 6 * naggr)] = sum;
+      }
     }
   }
 }
@@ -888,6 +924,59 @@ __device__ void grid_collect_window(const double* red, int slot, int nwg, double
 template <int NV>
 __device__ void grid_collect(const double* red, int slot, int nwg, double* sv) {
   grid_collect_window<NV>(red, slot, nwg, sv, nullptr, nullptr, 0);
+}
+
+// Coarse space of the upper-level preconditioner.  Aggregates are runs of
+// agg_sets consecutive sets (whole workgroups); each carries six affine
+// displacement fields about its centroid (X, Y), scaled by 1/E, written in
+// the set modes 1-6: for set s with tile centroid (x_s, y_s) and
+// dx = (x_s - X)/E, dy = (y_s - Y)/E the field u_x = (x - X)/E is
+// 0.5 * mode 3 + dx * mode 1, and likewise for the other three gradients.
+// The preconditioner is then the additive two-level B^+ + P0 A0^+ P0^T with
+// A0 = P0^T K_a P0, which involves only the constant modes 1-6.
+__device__ __forceinline__ void agg_coef(const Geo& g, const double* agg_xy, int agg_sets, int s,
+                                         double& dx, double& dy) {
+  const int a = s / agg_sets;
+  const int I = s % g.mx, J = s / g.mx;
+  const int i0 = I * g.E, j0 = J * g.E;
+  const int tw = min(g.E, g.nx - i0), th = min(g.E, g.ny - j0);
+  const double ic = i0 + 0.5 * (tw - 1), jc = j0 + 0.5 * (th - 1);
+  dx = (ic + 0.5 * jc - agg_xy[2 * a]) / g.E;
+  dy = (jc * kS3 - agg_xy[2 * a + 1]) / g.E;
+}
+
+// P0^T: the contribution of row (set, mode l) holding v to the six
+// aggregate-mode entries c[0..5].
+__device__ __forceinline__ void agg_restrict(int l, double v, double dx, double dy, double (&c)[6]) {
+  if (l == 0) { c[0] += v; c[2] += dx * v; c[3] += dy * v; }
+  else if (l == 1) { c[1] += v; c[4] += dx * v; c[5] += dy * v; }
+  else if (l < 6) c[l] += 0.5 * v;
+}
+
+// P0: the value on row (set, mode l) of the aggregate-mode vector y[0..5].
+__device__ __forceinline__ double agg_prolong(int l, const double* y, double dx, double dy) {
+  if (l == 0) return y[0] + dx * y[2] + dy * y[3];
+  if (l == 1) return y[1] + dx * y[4] + dy * y[5];
+  if (l < 6) return 0.5 * y[l];
+  return 0.0;
+}
+
+// y[v][r] = (A0^+ c[v]) on the rows r = 6 (a - a_lo) + k of the aggregates
+// a_lo .. a_lo + nwa - 1, whose rows of A0^+ are `rows` (in LDS): one wave
+// per row, lanes across the columns.
+__device__ void agg_window_solve(const double* rows, int naggr, int nwa, const double* c,
+                                 double* y, int nvec) {
+  const int n = 6 * naggr;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int r = wv; r < 6 * nwa; r += COARSE_NT / 64) {
+    const double* row = rows + (size_t)r * n;
+    for (int v = 0; v < nvec; ++v) {
+      double sum = 0.0;
+      for (int j = lane; j < n; j += 64) sum += row[j] * c[v * 6 * AGG_MAX + j];
+      sum = wave_sum(sum);
+      if (lane == 0) y[v * 6 * AGG_MAX + r] = sum;
+    }
+  }
 }
 
 // (K_a v) for one row of the workgroup's own sets, v from the LDS window that
@@ -926,13 +1015,35 @@ __device__ __forceinline__ double pinv_row(const double* bi, int s, int s0, int 
 
 }  // namespace
 
-// Dynamic LDS of the upper-level kernel: two windows of the set vectors and
-// the own rows of the vector being preconditioned, plus (when they fit) the
-// own sets' PCG vectors and their blocks.
+// m += P0 A0^+ P0^T w on the window: solve the window aggregates' rows of
+// A0^+ against the gathered restriction s_c, then add the prolongation to
+// the window copy of m (modes 1-6).  Ends synchronised.
+__device__ void coarse_space_correction(const Geo& g, const CoarseArgs& A, int a_lo, int nwa,
+                                        int w0, int win, const double* s_c, double* s_y,
+                                        double* lw, const double* lrows) {
+  agg_window_solve(lrows, A.naggr, nwa, s_c, s_y, 1);
+  __syncthreads();
+  for (int e = threadIdx.x; e < win * Q; e += COARSE_NT) {
+    const int l = e % Q;
+    if (l >= 6) continue;
+    const int ss = w0 + e / Q, al = ss / A.agg_sets - a_lo;
+    double dx, dy;
+    agg_coef(g, A.agg_xy, A.agg_sets, ss, dx, dy);
+    lw[e] += agg_prolong(l, s_y + 6 * al, dx, dy);
+  }
+  __syncthreads();
+}
+
+// Dynamic LDS of the upper-level kernel: two windows of the set vectors, the
+// own rows of the vector being preconditioned and the window aggregates'
+// rows of the coarse-space inverse, plus (when they fit) the own sets' PCG
+// vectors and their blocks.
 size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds) {
   const size_t spw = (size_t)(g.M + nwg - 1) / nwg;
   const size_t win = std::min((size_t)g.M, spw + 2 * (size_t)g.mx + 2);
+  const AggLayout al = agg_layout(g.M, g.mx, nwg);
   size_t b = (spw + 2 * win) * Q * sizeof(double);
+  b += (size_t)6 * al.nwa_max * 6 * al.naggr * sizeof(double);   // coarse-space rows
   if (vec_lds) b += 8 * spw * Q * sizeof(double);
   if (blk_lds) b += spw * (NDIR + 2) * Q * Q * sizeof(double);
   return b;
@@ -957,6 +1068,13 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   const int win = ns > 0 ? w1 - w0 : 0;
   const int nrow = ns * Q;
   const unsigned spin = A.spin_limit;
+  // coarse space: restrictions (two vectors at the start) and the window
+  // aggregates' corrections
+  const bool two = A.naggr > 0;
+  __shared__ double s_c[2 * 6 * AGG_MAX];
+  __shared__ double s_y[2 * 6 * AGG_MAX];
+  const int a_lo = two && win > 0 ? w0 / A.agg_sets : 0;
+  const int nwa = two && win > 0 ? (w1 - 1) / A.agg_sets - a_lo + 1 : 0;
   const unsigned base = ctrl->bar_gen;
   const int iter = ctrl->k;
   unsigned nsync = 0;
@@ -965,7 +1083,9 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   double* lown = lds;                          // own rows of the vector being preconditioned
   double* lw1 = lown + (size_t)spw * Q;        // window (first vector)
   double* lw2 = lw1 + (size_t)wmax * Q;        // window (second vector)
-  double* lnext = lw2 + (size_t)wmax * Q;
+  double* lrows = lw2 + (size_t)wmax * Q;     // window aggregates' rows of A0^+
+  const AggLayout alay = agg_layout(M, g.mx, nwg);
+  double* lnext = lrows + (size_t)6 * alay.nwa_max * 6 * alay.naggr;
   const size_t r0 = (size_t)s0 * Q;            // first own row
   // Own-row vectors, touched only by the owning thread: in LDS when they fit,
   // else in global memory.  All are indexed from the workgroup's first row.
@@ -999,6 +1119,12 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     __syncthreads();
   }
 
+  if (two) {   // the window aggregates' rows of A0^+, once per launch
+    const int n = 6 * A.naggr;
+    for (int e = t; e < 6 * nwa * n; e += COARSE_NT) lrows[e] = A.agg_inv[(size_t)6 * a_lo * n + e];
+    __syncthreads();
+  }
+
   // --- start.  The warm start x0 = theta a_prev takes the previous solve's
   //     coefficients scaled by the step that minimises the upper-level
   //     energy along them (so the outer energy still decreases).  With
@@ -1009,7 +1135,12 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   const bool warm = A.warm && iter > 0;
   for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = warm ? A.a[(size_t)w0 * Q + e] : 0.0;
   __syncthreads();
-  double red6[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // [0..3] stop-test norms, [4..5] theta's dot products, [6] P . B^+ P,
+  // [7..12] P0^T P, [13..18] P0^T y (coarse space)
+  double red6[19];
+#pragma unroll
+  for (int v = 0; v < 19; ++v) red6[v] = 0.0;
+  double cP[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, cY[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int s = s0 + t; s < s1; s += COARSE_NT) {
 #pragma unroll
     for (int v = 0; v < NRM; ++v) red6[v] += A.nrm[(size_t)s * NRM + v];
@@ -1022,6 +1153,17 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     red6[5] += aprev * y;
     vn[e] = y;                   // keep y for r0
     lown[e] = A.force[r0 + e];
+    if (two && m < 6) {
+      double dx, dy;
+      agg_coef(g, A.agg_xy, A.agg_sets, s, dx, dy);
+      agg_restrict(m, A.force[r0 + e], dx, dy, cP);
+      agg_restrict(m, y, dx, dy, cY);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    red6[7 + k] = cP[k];
+    red6[13 + k] = cY[k];
   }
   __syncthreads();
   for (int e = t; e < nrow; e += COARSE_NT) {
@@ -1040,9 +1182,11 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     pub_store(&A.pub1[r0 + e], v);    // B^+ y
     vq[e] = v;
   }
-  if (!grid_publish_wait<7>(red6, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
+  if (!grid_publish_wait<19>(red6, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
     return;
-  grid_collect<7>(A.red, slot, nwg, sv);
+  grid_collect_window<7, 2>(A.red, slot, nwg, sv, nullptr, nullptr, 0, 7, two ? 2 : 0, A.agg_g,
+                            A.naggr, s_c);
+  if (two && nwg == 1 && t < 12) s_c[(t / 6) * 6 * AGG_MAX + t % 6] = sv[7 + t];
   slot ^= 1;
   __syncthreads();
 #pragma unroll
@@ -1070,15 +1214,30 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     if (status != -100) return;
   }
   const double theta = (warm && red6[5] > 0.0 && red6[4] > 0.0) ? red6[4] / red6[5] : 0.0;
+  // coarse-space parts of B^+ P and B^+ y on the window's aggregates
+  if (two) {
+    agg_window_solve(lrows, A.naggr, nwa, s_c, s_y, 2);
+    __syncthreads();
+  }
   // x0, r0, u0 (own) and u0 over the window, then w0 = K_a u0
   for (int e = t; e < win * Q; e += COARSE_NT) {
     const size_t ge = (size_t)w0 * Q + e;
-    lw2[e] = pub_load(&A.pub0[ge]) - theta * pub_load(&A.pub1[ge]);
+    double v = pub_load(&A.pub0[ge]) - theta * pub_load(&A.pub1[ge]);
+    if (two && e % Q < 6) {
+      const int ss = w0 + e / Q, al = ss / A.agg_sets - a_lo;
+      double dx, dy, yv[6];
+      agg_coef(g, A.agg_xy, A.agg_sets, ss, dx, dy);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) yv[k] = s_y[6 * al + k] - theta * s_y[6 * AGG_MAX + 6 * al + k];
+      v += agg_prolong(e % Q, yv, dx, dy);
+    }
+    lw2[e] = v;
   }
+  __syncthreads();
   for (int e = t; e < nrow; e += COARSE_NT) {
     vx[e] = theta * lw1[(size_t)(s0 - w0) * Q + e];
     vr[e] = A.force[r0 + e] - theta * vn[e];
-    vu[e] = vz[e] - theta * vq[e];
+    vu[e] = lw2[(size_t)(s0 - w0) * Q + e];     // M^-1 r0 on the own rows
   }
   __syncthreads();
   for (int e = t; e < nrow; e += COARSE_NT) {
@@ -1119,21 +1278,32 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     const int sown = (s - w0) * Q, sset = (s - s0) * Q;
     double x = own ? vx[t] : 0.0, r = own ? vr[t] : 0.0, u = own ? vu[t] : 0.0;
     double wv = own ? vw[t] : 0.0, z = 0.0, q = 0.0, sv_ = 0.0, p = 0.0;
+    double rdx = 0.0, rdy = 0.0;
+    if (two && own) agg_coef(g, A.agg_xy, A.agg_sets, s, rdx, rdy);
     for (;; ++it) {
-      double gd[2] = {r * u, wv * u};
+      // the two dot products and the coarse-space restriction of w
+      double gd[8] = {r * u, wv * u, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (two && own) {
+        double c6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        agg_restrict(m, wv, rdx, rdy, c6);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) gd[2 + k] = c6[k];
+      }
       if (own) lown[t] = wv;
       __syncthreads();
       double mv = 0.0;
 #pragma unroll
       for (int l = 0; l < Q; ++l) mv += birow[l] * lown[sset + l];
-      double* mpub = (it & 1) ? A.pub1 : A.pub0;
+      double* mpub = (it & 1) ? A.pub0 : A.pub2;
       if (own) {
         if (nwg == 1) lw1[t] = mv;
         else pub_store(&mpub[r0 + t], mv);
       }
-      if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
+      if (!grid_publish_wait<8>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
         return;
-      grid_collect_window<2>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q);
+      grid_collect_window<2>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q, 2,
+                             two ? 1 : 0, A.agg_g, A.naggr, s_c);
+      if (two && nwg == 1 && t < 6) s_c[t] = sv[2 + t];
       slot ^= 1;
       __syncthreads();
       const double gamma = sv[0], delta = sv[1];
@@ -1150,6 +1320,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
         alpha = den > 0.0 ? gamma / den : 0.0;
       }
       if (!(alpha > 0.0)) break;
+      if (two) coarse_space_correction(g, A, a_lo, nwa, w0, win, s_c, s_y, lw1, lrows);
       double n = 0.0;
 #pragma unroll
       for (int l = 0; l < Q; ++l) n += brow[l] * lw1[sown + l];
@@ -1173,25 +1344,36 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     if (own) vx[t] = x;
   } else
   for (;; ++it) {
-    // dot products of this iteration, and m = B^+ w published for the neighbours
-    double gd[2] = {0.0, 0.0};
+    // dot products of this iteration, the coarse-space restriction of w, and
+    // m = B^+ w published for the neighbours
+    double gd[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double c6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int e = t; e < nrow; e += COARSE_NT) {
       const double u = vu[e], wv = vw[e];
       gd[0] += vr[e] * u;
       gd[1] += wv * u;
       lown[e] = wv;
+      if (two && e % Q < 6) {
+        double dx, dy;
+        agg_coef(g, A.agg_xy, A.agg_sets, s0 + e / Q, dx, dy);
+        agg_restrict(e % Q, wv, dx, dy, c6);
+      }
     }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gd[2 + k] = c6[k];
     __syncthreads();
-    double* mpub = (it & 1) ? A.pub1 : A.pub0;
+    double* mpub = (it & 1) ? A.pub0 : A.pub2;
     for (int e = t; e < nrow; e += COARSE_NT) {
       const double mv = pinv_row(bi, s0 + e / Q, s0, e % Q, lown);
       if (nwg == 1) lw1[e] = mv;            // one workgroup: the window is its own sets
       else pub_store(&mpub[r0 + e], mv);
     }
-    if (!grid_publish_wait<2>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
+    if (!grid_publish_wait<8>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
       return;
-    // one round trip: the partial sums and the neighbours' m together
-    grid_collect_window<2>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q);
+    // one round trip: the partial sums, the restrictions and the neighbours' m
+    grid_collect_window<2>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q, 2,
+                           two ? 1 : 0, A.agg_g, A.naggr, s_c);
+    if (two && nwg == 1 && t < 6) s_c[t] = sv[2 + t];
     slot ^= 1;
     __syncthreads();
     const double gamma = sv[0], delta = sv[1];
@@ -1208,6 +1390,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
       alpha = den > 0.0 ? gamma / den : 0.0;
     }
     if (!(alpha > 0.0)) break;
+    if (two) coarse_space_correction(g, A, a_lo, nwa, w0, win, s_c, s_y, lw1, lrows);
     for (int e = t; e < nrow; e += COARSE_NT) {
       const double n = coarse_row(g, bd, ob, s0 + e / Q, s0, e % Q, lw1, w0);
       const double m = lw1[(size_t)(s0 - w0) * Q + e];
@@ -1249,10 +1432,130 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
 
 // Fused launch: lattice b owns workgroups [wg0, wg0 + nwg) and runs its own
 // grid sums among them; the launch is sized to be co-resident.
-__global__ __launch_bounds__(COARSE_NT) void k_coarse_batch(const BatchEntry* __restrict__ B,
+// (two workgroups per CU, so that fused batches keep their co-resident capacity)
+__global__ __launch_bounds__(COARSE_NT, 2) void k_coarse_batch(const BatchEntry* __restrict__ B,
                                                             const int* __restrict__ wg_lat) {
   const BatchEntry& e = B[wg_lat[blockIdx.x]];
   coarse_body(e.g, e.ca, blockIdx.x - e.wg0, e.nwg);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse space of the upper-level preconditioner, set up once per lattice.
+// ---------------------------------------------------------------------------
+namespace {
+// Entry [m][k] of set s's slice of P0: set mode m (0..5) in aggregate mode k.
+__device__ __forceinline__ double agg_p(int m, int k, double dx, double dy) {
+  if (m == 0) return k == 0 ? 1.0 : k == 2 ? dx : k == 3 ? dy : 0.0;
+  if (m == 1) return k == 1 ? 1.0 : k == 4 ? dx : k == 5 ? dy : 0.0;
+  return k == m ? 0.5 : 0.0;
+}
+}  // namespace
+
+// Block row a of A0 = P0^T K_a P0 from the constant mode 1-6 blocks: the
+// set's own block g1 and the 6 x 6 corners of its neighbour blocks.  Thread
+// (k, k') < 36 owns entry (k, k') of every 6 x 6 block of the row and adds
+// the sets' contributions in a fixed order.
+__global__ __launch_bounds__(64) void k_agg_assemble(Geo g, const double* __restrict__ g1,
+                                                     const double* __restrict__ off,
+                                                     const double* __restrict__ agg_xy,
+                                                     int agg_sets, int naggr, double* A0) {
+  __shared__ double row[6 * 6 * AGG_MAX];
+  const int a = blockIdx.x, t = threadIdx.x, n = 6 * naggr;
+  for (int e = t; e < 6 * n; e += 64) row[e] = 0.0;
+  __syncthreads();
+  if (t < 36) {
+    const int k = t / 6, kp = t % 6;
+    const int sa = a * agg_sets, sb = min(g.M, sa + agg_sets);
+    for (int I = sa; I < sb; ++I) {
+      double dxI, dyI;
+      agg_coef(g, agg_xy, agg_sets, I, dxI, dyI);
+      const int Ii = I % g.mx, Ij = I / g.mx;
+      for (int d = -1; d < NDIR; ++d) {
+        int J = I;
+        if (d >= 0) {
+          const int I2 = Ii + nb_di(d), J2 = Ij + nb_dj(d);
+          if (I2 < 0 || I2 >= g.mx || J2 < 0 || J2 >= g.my) continue;
+          J = J2 * g.mx + I2;
+        }
+        double dxJ, dyJ;
+        agg_coef(g, agg_xy, agg_sets, J, dxJ, dyJ);
+        double c = 0.0;
+        for (int m = 0; m < 6; ++m) {
+          const double pm = agg_p(m, k, dxI, dyI);
+          if (pm == 0.0) continue;
+          double kl = 0.0;
+          for (int l = 0; l < 6; ++l) {
+            const double pl = agg_p(l, kp, dxJ, dyJ);
+            if (pl == 0.0) continue;
+            const double kml = d < 0 ? g1[(size_t)I * 36 + m * 6 + l]
+                                     : off[((size_t)I * NDIR + d) * Q * Q + m * Q + l];
+            kl += kml * pl;
+          }
+          c += pm * kl;
+        }
+        row[k * n + 6 * (J / agg_sets) + kp] += c;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < 6 * n; e += 64) A0[(size_t)(6 * a + e / n) * n + e % n] = row[e];
+}
+
+// In place: A0 -> its pseudo-inverse.  Symmetric Jacobi scaling, then
+// Gauss-Jordan elimination without row exchanges (A0 is symmetric positive
+// semidefinite) that drops a variable whose pivot falls below 1e-9 (it is,
+// to that level, a combination of the variables before it), then the
+// scaling back and a symmetrisation.  One workgroup.
+__global__ __launch_bounds__(1024) void k_agg_invert(double* A, int n) {
+  __shared__ double sc[6 * AGG_MAX], rowk[6 * AGG_MAX], colk[6 * AGG_MAX];
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int i = t; i < n; i += nt) {
+    const double d = A[(size_t)i * n + i];
+    sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < n * n; e += nt) A[e] *= sc[e / n] * sc[e % n];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double p = A[(size_t)k * n + k];
+    const bool keep = p > 1e-9;
+    for (int j = t; j < n; j += nt) {
+      rowk[j] = keep ? (j == k ? 1.0 / p : A[(size_t)k * n + j] / p) : 0.0;
+      colk[j] = keep && j != k ? A[(size_t)j * n + k] : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < n * n; e += nt) {
+      const int i = e / n, j = e % n;
+      if (!keep) {
+        if (i == k || j == k) A[e] = 0.0;
+      } else if (i == k) {
+        A[e] = rowk[j];
+      } else {
+        A[e] = (j == k ? 0.0 : A[e]) - colk[i] * rowk[j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += nt) {
+    const int i = e / n, j = e % n;
+    if (i <= j) {
+      const double v = 0.5 * (A[e] + A[(size_t)j * n + i]) * sc[i] * sc[j];
+      A[e] = v;
+      A[(size_t)j * n + i] = v;
+    }
+  }
+}
+
+hipError_t launch_agg_setup(const Geo& g, const double* g1, const double* off,
+                            const double* agg_xy, int agg_sets, int naggr, double* A0,
+                            hipStream_t stream) {
+  if (naggr <= 0 || naggr > AGG_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_agg_assemble, dim3(naggr), dim3(64), 0, stream, g, g1, off, agg_xy,
+                     agg_sets, naggr, A0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_agg_invert, dim3(1), dim3(1024), 0, stream, A0, 6 * naggr);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1574,7 +1877,7 @@ int coarse_batch_capacity(size_t lds) {
   static bool attr_set = false;
   if (!attr_set) {
     if (hipFuncSetAttribute((const void*)k_coarse_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024 - 1024) != hipSuccess)
+                            COARSE_DYN_LDS_MAX) != hipSuccess)
       return 0;
     attr_set = true;
   }
@@ -1627,12 +1930,12 @@ hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream) 
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_coarse,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, COARSE_DYN_LDS_MAX);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const size_t lds = coarse_lds_bytes(g, a.nwg, a.vec_lds, a.blk_lds);
-  if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  if (lds > COARSE_DYN_LDS_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_coarse, dim3(a.nwg), dim3(COARSE_NT), lds, stream, g, a);
   return hipGetLastError();
 }

@@ -25,6 +25,7 @@ struct Work {
   double *bdiag = nullptr, *binv = nullptr;
   double *cr = nullptr, *cu = nullptr, *cw = nullptr, *cz = nullptr, *cq = nullptr;
   double *cs = nullptr, *cp = nullptr, *cn = nullptr, *pub0 = nullptr, *pub1 = nullptr;
+  double* pub2 = nullptr;
   double *red = nullptr, *hist = nullptr;
   Ctrl* ctrl = nullptr;
   unsigned* flags = nullptr;       // grid-sum arrival flags of the upper-level kernel
@@ -65,6 +66,12 @@ struct tl_lattice {
   double* res_part = nullptr;   // certification scratch
   double* res_out = nullptr;
   double* out5_host = nullptr;  // pinned
+  // coarse space of the upper-level preconditioner (built on first solve)
+  double* agg_inv = nullptr;    // [6 naggr][6 naggr]
+  double* agg_xy = nullptr;     // [naggr][2] aggregate centroids
+  int naggr = 0, agg_sets = 0, agg_g = 0, agg_nwg = 0;
+  bool agg_ready = false;
+  std::mutex agg_mu;
 };
 
 namespace tl {
@@ -78,6 +85,10 @@ struct CoarseShape {
 };
 CoarseShape coarse_shape(const Geo& g);
 tl_status resolve_opts(const tl_opts* o, Opts* r);
+// Build the lattice's upper-level coarse space once (needs one solve state
+// just initialised by its init kernel); synchronises the stream.
+tl_status ensure_coarse_space(tl_lattice* L, Work* w, const Opts& o, const double* f,
+                              hipStream_t st);
 void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const double* f,
                          TileArgs* ta, OffArgs* oa, BlockArgs* ba, CoarseArgs* ca);
 tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const double* f,
