@@ -1018,18 +1018,16 @@ __device__ __forceinline__ double pinv_row(const double* bi, int s, int s0, int 
 // m += P0 A0^+ P0^T w on the window: solve the window aggregates' rows of
 // A0^+ against the gathered restriction s_c, then add the prolongation to
 // the window copy of m (modes 1-6).  Ends synchronised.
-__device__ void coarse_space_correction(const Geo& g, const CoarseArgs& A, int a_lo, int nwa,
-                                        int w0, int win, const double* s_c, double* s_y,
-                                        double* lw, const double* lrows) {
+__device__ void coarse_space_correction(const CoarseArgs& A, int nwa, int win,
+                                        const double* s_c, double* s_y, double* lw,
+                                        const double* lrows, const double* ldxy) {
   agg_window_solve(lrows, A.naggr, nwa, s_c, s_y, 1);
   __syncthreads();
   for (int e = threadIdx.x; e < win * Q; e += COARSE_NT) {
-    const int l = e % Q;
+    const int sl = e / Q, l = e - Q * sl;
     if (l >= 6) continue;
-    const int ss = w0 + e / Q, al = ss / A.agg_sets - a_lo;
-    double dx, dy;
-    agg_coef(g, A.agg_xy, A.agg_sets, ss, dx, dy);
-    lw[e] += agg_prolong(l, s_y + 6 * al, dx, dy);
+    const double* d = ldxy + 3 * sl;
+    lw[e] += agg_prolong(l, s_y + 6 * (int)d[2], d[0], d[1]);
   }
   __syncthreads();
 }
@@ -1044,6 +1042,7 @@ size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds) {
   const AggLayout al = agg_layout(g.M, g.mx, nwg);
   size_t b = (spw + 2 * win) * Q * sizeof(double);
   b += (size_t)6 * al.nwa_max * 6 * al.naggr * sizeof(double);   // coarse-space rows
+  b += 3 * win * sizeof(double);                                  // P0 entries of the window
   if (vec_lds) b += 8 * spw * Q * sizeof(double);
   if (blk_lds) b += spw * (NDIR + 2) * Q * Q * sizeof(double);
   return b;
@@ -1085,7 +1084,8 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   double* lw2 = lw1 + (size_t)wmax * Q;        // window (second vector)
   double* lrows = lw2 + (size_t)wmax * Q;     // window aggregates' rows of A0^+
   const AggLayout alay = agg_layout(M, g.mx, nwg);
-  double* lnext = lrows + (size_t)6 * alay.nwa_max * 6 * alay.naggr;
+  double* ldxy = lrows + (size_t)6 * alay.nwa_max * 6 * alay.naggr;  // [wmax][3]: dx, dy, aggregate
+  double* lnext = ldxy + (size_t)3 * wmax;
   const size_t r0 = (size_t)s0 * Q;            // first own row
   // Own-row vectors, touched only by the owning thread: in LDS when they fit,
   // else in global memory.  All are indexed from the workgroup's first row.
@@ -1119,9 +1119,16 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     __syncthreads();
   }
 
-  if (two) {   // the window aggregates' rows of A0^+, once per launch
+  if (two) {   // the window aggregates' rows of A0^+ and P0's entries, once per launch
     const int n = 6 * A.naggr;
     for (int e = t; e < 6 * nwa * n; e += COARSE_NT) lrows[e] = A.agg_inv[(size_t)6 * a_lo * n + e];
+    for (int e = t; e < win; e += COARSE_NT) {
+      double dx, dy;
+      agg_coef(g, A.agg_xy, A.agg_sets, w0 + e, dx, dy);
+      ldxy[3 * e] = dx;
+      ldxy[3 * e + 1] = dy;
+      ldxy[3 * e + 2] = (double)((w0 + e) / A.agg_sets - a_lo);
+    }
     __syncthreads();
   }
 
@@ -1224,12 +1231,12 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     const size_t ge = (size_t)w0 * Q + e;
     double v = pub_load(&A.pub0[ge]) - theta * pub_load(&A.pub1[ge]);
     if (two && e % Q < 6) {
-      const int ss = w0 + e / Q, al = ss / A.agg_sets - a_lo;
-      double dx, dy, yv[6];
-      agg_coef(g, A.agg_xy, A.agg_sets, ss, dx, dy);
+      const double* d = ldxy + 3 * (e / Q);
+      const int al = (int)d[2];
+      double yv[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) yv[k] = s_y[6 * al + k] - theta * s_y[6 * AGG_MAX + 6 * al + k];
-      v += agg_prolong(e % Q, yv, dx, dy);
+      v += agg_prolong(e % Q, yv, d[0], d[1]);
     }
     lw2[e] = v;
   }
@@ -1320,7 +1327,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
         alpha = den > 0.0 ? gamma / den : 0.0;
       }
       if (!(alpha > 0.0)) break;
-      if (two) coarse_space_correction(g, A, a_lo, nwa, w0, win, s_c, s_y, lw1, lrows);
+      if (two) coarse_space_correction(A, nwa, win, s_c, s_y, lw1, lrows, ldxy);
       double n = 0.0;
 #pragma unroll
       for (int l = 0; l < Q; ++l) n += brow[l] * lw1[sown + l];
@@ -1354,9 +1361,8 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
       gd[1] += wv * u;
       lown[e] = wv;
       if (two && e % Q < 6) {
-        double dx, dy;
-        agg_coef(g, A.agg_xy, A.agg_sets, s0 + e / Q, dx, dy);
-        agg_restrict(e % Q, wv, dx, dy, c6);
+        const double* d = ldxy + 3 * (s0 - w0 + e / Q);
+        agg_restrict(e % Q, wv, d[0], d[1], c6);
       }
     }
 #pragma unroll
@@ -1390,7 +1396,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
       alpha = den > 0.0 ? gamma / den : 0.0;
     }
     if (!(alpha > 0.0)) break;
-    if (two) coarse_space_correction(g, A, a_lo, nwa, w0, win, s_c, s_y, lw1, lrows);
+    if (two) coarse_space_correction(A, nwa, win, s_c, s_y, lw1, lrows, ldxy);
     for (int e = t; e < nrow; e += COARSE_NT) {
       const double n = coarse_row(g, bd, ob, s0 + e / Q, s0, e % Q, lw1, w0);
       const double m = lw1[(size_t)(s0 - w0) * Q + e];
