@@ -87,15 +87,16 @@ bool plan_coarse(const std::vector<const Geo*>& gs, std::vector<int>* nw_out,
   static const size_t classes[2] = {64 * 1024, COARSE_DYN_LDS_MAX};
   for (size_t cap : classes) {
     bool ok = true;
-    for (int b = 0; b < n && ok; ++b) ok = coarse_lds_bytes(*gs[b], nw[b], 0, 0) <= cap;
+    for (int b = 0; b < n && ok; ++b) ok = coarse_lds_bytes(*gs[b], nw[b], 0, 0, shape[b].two_level) <= cap;
     if (!ok || coarse_batch_capacity(cap) < used) continue;
     size_t lds = 0;
     for (int b = 0; b < n; ++b) {
-      const int vec = shape[b].vec_lds && coarse_lds_bytes(*gs[b], nw[b], 1, 0) <= cap;
-      const int blk = vec && shape[b].blk_lds && coarse_lds_bytes(*gs[b], nw[b], 1, 1) <= cap;
+      const int vec = shape[b].vec_lds && coarse_lds_bytes(*gs[b], nw[b], 1, 0, shape[b].two_level) <= cap;
+      const int blk = vec && shape[b].blk_lds &&
+                      coarse_lds_bytes(*gs[b], nw[b], 1, 1, shape[b].two_level) <= cap;
       shape[b].vec_lds = vec;
       shape[b].blk_lds = blk;
-      lds = std::max(lds, coarse_lds_bytes(*gs[b], nw[b], vec, blk));
+      lds = std::max(lds, coarse_lds_bytes(*gs[b], nw[b], vec, blk, shape[b].two_level));
     }
     *nw_out = nw;
     *shape_out = shape;

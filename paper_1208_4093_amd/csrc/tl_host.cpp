@@ -129,9 +129,10 @@ CoarseShape coarse_shape(const Geo& g) {
   const int per = std::max(1, env_int("TL_COARSE_SETS_PER_WG", 16));
   CoarseShape c;
   c.nwg = std::max(1, std::min((g.M + per - 1) / per, COARSE_MAX_WG));
-  while (c.nwg < COARSE_MAX_WG && coarse_lds_bytes(g, c.nwg, 0, 0) > kCoarseLdsCap) ++c.nwg;
-  c.vec_lds = coarse_lds_bytes(g, c.nwg, 1, 0) <= kCoarseLdsCap;
-  c.blk_lds = c.vec_lds && coarse_lds_bytes(g, c.nwg, 1, 1) <= kCoarseLdsCap;
+  while (c.nwg < COARSE_MAX_WG && coarse_lds_bytes(g, c.nwg, 0, 0, 0) > kCoarseLdsCap) ++c.nwg;
+  c.two_level = coarse_lds_bytes(g, c.nwg, 0, 0, 1) <= kCoarseLdsCap;
+  c.vec_lds = coarse_lds_bytes(g, c.nwg, 1, 0, c.two_level) <= kCoarseLdsCap;
+  c.blk_lds = c.vec_lds && coarse_lds_bytes(g, c.nwg, 1, 1, c.two_level) <= kCoarseLdsCap;
   if (env_int("TL_COARSE_NO_LDS", 0)) c.vec_lds = c.blk_lds = 0;
   return c;
 }
@@ -225,7 +226,8 @@ void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const doub
   ca->vec_lds = cs.vec_lds;
   ca->blk_lds = cs.blk_lds;
   // the coarse space, when built and laid out for this workgroup count
-  const bool two = L->agg_ready && L->agg_nwg == cs.nwg && env_int("TL_COARSE_2LEVEL", 1) != 0;
+  const bool two = L->agg_ready && L->naggr > 0 && cs.two_level && L->agg_nwg == cs.nwg &&
+                   env_int("TL_COARSE_2LEVEL", 1) != 0;
   ca->agg_inv = two ? L->agg_inv : nullptr;
   ca->agg_xy = two ? L->agg_xy : nullptr;
   ca->naggr = two ? L->naggr : 0;
@@ -235,7 +237,7 @@ void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const doub
 
 tl_status ensure_coarse_space(tl_lattice* L, Work* w, const Opts& o, const double* f,
                               hipStream_t st) {
-  if (L->agg_ready || env_int("TL_COARSE_2LEVEL", 1) == 0) return TL_OK;
+  if (L->agg_ready || L->naggr == 0 || env_int("TL_COARSE_2LEVEL", 1) == 0) return TL_OK;
   std::lock_guard<std::mutex> lock(L->agg_mu);
   if (L->agg_ready) return TL_OK;
   // the boundary blocks of the just-initialised state (relaxation increments
@@ -516,8 +518,9 @@ tl_status tl_lattice_create(const tl_lattice_desc* desc, void* hip_stream, tl_la
     if (e != hipSuccess) return fail(from_hip(e));
   }
   // Coarse space of the upper-level preconditioner: aggregates of whole
-  // upper-level workgroups (at most AGG_MAX of them), centroids on the host.
-  {
+  // upper-level workgroups (at most AGG_MAX of them), centroids on the host;
+  // none when its LDS would not fit beside the upper-level windows.
+  if (coarse_shape(L->g).two_level) {
     const CoarseShape cs = coarse_shape(L->g);
     const int M = L->g.M;
     const AggLayout al = agg_layout(M, L->g.mx, cs.nwg);

@@ -189,7 +189,7 @@ hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8
                           const OffArgs& a, hipStream_t stream);
 hipError_t launch_blockinv(const Geo& g, const BlockArgs& a, hipStream_t stream);
 hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream);
-size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds);
+size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds, int two_level);
 // Coarse space of the upper-level preconditioner: A0 = P0^T K_a P0 from the
 // constant blocks (g1 and the mode 1-6 corners of off), then its
 // pseudo-inverse in place.

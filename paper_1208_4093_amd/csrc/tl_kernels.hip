@@ -71,28 +71,31 @@ __device__ __forceinline__ double wave_max(double v) {
 // values it still holds and adds the partner's copy of that half, so after
 // the six steps lane l holds the wave total of value l >> (6 - log2 V).
 // Lanes that end with the same value hold the same bits.
+//
+// One halving step at lane offset O with H values still held; every index
+// is a compile-time constant, so v stays in registers.
+template <int V, int H, int O>
+__device__ __forceinline__ void wave_sums_step(double (&v)[V], int lane) {
+  if constexpr (H > 1) {
+    constexpr int h = H / 2;
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int j = 0; j < h; ++j) {
+      const double send = up ? v[j] : v[j + h];
+      const double keep = up ? v[j + h] : v[j];
+      v[j] = keep + __shfl_xor(send, O, 64);
+    }
+    if constexpr (O > 1) wave_sums_step<V, h, O / 2>(v, lane);
+  } else {
+    v[0] += __shfl_xor(v[0], O, 64);
+    if constexpr (O > 1) wave_sums_step<V, 1, O / 2>(v, lane);
+  }
+}
+
 template <int V>
 __device__ __forceinline__ double wave_sums(double (&v)[V]) {
   static_assert(V >= 1 && V <= 64 && (V & (V - 1)) == 0, "V must be a power of two <= 64");
-  const int lane = threadIdx.x & 63;
-  int h = V;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    if (h > 1) {
-      h >>= 1;
-      const bool up = (lane & o) != 0;
-#pragma unroll
-      for (int j = 0; j < V / 2; ++j) {
-        if (j < h) {
-          const double send = up ? v[j] : v[j + h];
-          const double keep = up ? v[j + h] : v[j];
-          v[j] = keep + __shfl_xor(send, o, 64);
-        }
-      }
-    } else {
-      v[0] += __shfl_xor(v[0], o, 64);
-    }
-  }
+  wave_sums_step<V, V, 32>(v, threadIdx.x & 63);
   return v[0];
 }
 
@@ -1036,13 +1039,15 @@ __device__ void coarse_space_correction(const CoarseArgs& A, int nwa, int win,
 // own rows of the vector being preconditioned and the window aggregates'
 // rows of the coarse-space inverse, plus (when they fit) the own sets' PCG
 // vectors and their blocks.
-size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds) {
+size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds, int two_level) {
   const size_t spw = (size_t)(g.M + nwg - 1) / nwg;
   const size_t win = std::min((size_t)g.M, spw + 2 * (size_t)g.mx + 2);
-  const AggLayout al = agg_layout(g.M, g.mx, nwg);
   size_t b = (spw + 2 * win) * Q * sizeof(double);
-  b += (size_t)6 * al.nwa_max * 6 * al.naggr * sizeof(double);   // coarse-space rows
-  b += 3 * win * sizeof(double);                                  // P0 entries of the window
+  if (two_level) {
+    const AggLayout al = agg_layout(g.M, g.mx, nwg);
+    b += (size_t)6 * al.nwa_max * 6 * al.naggr * sizeof(double);   // coarse-space rows
+    b += 3 * win * sizeof(double);                                  // P0 entries of the window
+  }
   if (vec_lds) b += 8 * spw * Q * sizeof(double);
   if (blk_lds) b += spw * (NDIR + 2) * Q * Q * sizeof(double);
   return b;
@@ -1084,8 +1089,9 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   double* lw2 = lw1 + (size_t)wmax * Q;        // window (second vector)
   double* lrows = lw2 + (size_t)wmax * Q;     // window aggregates' rows of A0^+
   const AggLayout alay = agg_layout(M, g.mx, nwg);
-  double* ldxy = lrows + (size_t)6 * alay.nwa_max * 6 * alay.naggr;  // [wmax][3]: dx, dy, aggregate
-  double* lnext = ldxy + (size_t)3 * wmax;
+  const size_t nrows_lds = two ? (size_t)6 * alay.nwa_max * 6 * alay.naggr : 0;
+  double* ldxy = lrows + nrows_lds;                     // [wmax][3]: dx, dy, aggregate
+  double* lnext = ldxy + (two ? (size_t)3 * wmax : 0);
   const size_t r0 = (size_t)s0 * Q;            // first own row
   // Own-row vectors, touched only by the owning thread: in LDS when they fit,
   // else in global memory.  All are indexed from the workgroup's first row.
@@ -1940,7 +1946,7 @@ hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream) 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  const size_t lds = coarse_lds_bytes(g, a.nwg, a.vec_lds, a.blk_lds);
+  const size_t lds = coarse_lds_bytes(g, a.nwg, a.vec_lds, a.blk_lds, a.naggr > 0);
   if (lds > COARSE_DYN_LDS_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_coarse, dim3(a.nwg), dim3(COARSE_NT), lds, stream, g, a);
   return hipGetLastError();

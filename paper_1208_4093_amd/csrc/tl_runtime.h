@@ -82,6 +82,7 @@ size_t padded_nodes(const Geo& g);
 size_t work_bytes(const Geo& g, bool mixed, int hist_cap);
 struct CoarseShape {
   int nwg, vec_lds, blk_lds;
+  int two_level;      // the coarse space's LDS fits beside the windows
 };
 CoarseShape coarse_shape(const Geo& g);
 tl_status resolve_opts(const tl_opts* o, Opts* r);
