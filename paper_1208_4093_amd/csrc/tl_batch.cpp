@@ -69,7 +69,7 @@ struct Job {
 // and in any batch.  All workgroups of the launch must be co-resident (each
 // lattice's grid sums wait on its own workgroups), so the plan picks an LDS
 // size class (64 KB: two workgroups per CU beside the static arrays; else
-// 144 KB: one) that every
+// 152 KB: one) that every
 // lattice's unstaged slice fits, checks the total against the co-resident
 // capacity at that class, and enables LDS staging per lattice where it still
 // fits the class.  Returns false when the lattices cannot all be co-resident.

@@ -33,8 +33,8 @@ constexpr int REDW = 24;        // values per workgroup and slot of a grid sum
 constexpr int AGG_MAX = 32;     // aggregates of the upper-level coarse space (at most)
 constexpr int AGG_GMAX = 8;     // workgroups per aggregate (at most: COARSE_MAX_WG / AGG_MAX)
 // Dynamic LDS of one upper-level workgroup, at most: the 160 KB of a CU less
-// the kernel's static arrays (grid-sum and coarse-space scratch, under 16 KB).
-constexpr size_t COARSE_DYN_LDS_MAX = 144 * 1024;
+// the kernel's static arrays (grid-sum and coarse-space scratch, 7 KB).
+constexpr size_t COARSE_DYN_LDS_MAX = 152 * 1024;
 constexpr int LPAD = 32;        // left padding (elements) of node arrays: interior
                                 // rows start on a 128-byte boundary for every type
 
