@@ -846,13 +846,12 @@ __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* 
 // agg_k0 + 6 v + k of the agg_g workgroups of aggregate a.  All loads are
 // issued before any is used, so they take one memory round trip together.
 // Only the collecting threads write sv / s_c; the caller synchronises.
-template <int NV, int NVEC = 1>
+template <int NV, int NVEC = 1, int WB = 4>
 __device__ void grid_collect_window(const double* red, int slot, int nwg, double* sv,
                                     double* dst, const double* src, int n,
                                     int agg_k0 = 0, int agg_nvec = 0, int agg_g = 1,
                                     int naggr = 0, double* s_c = nullptr) {
   constexpr int PW = COARSE_MAX_WG / 64;
-  constexpr int WB = 4;
   constexpr int CB = (NVEC * 6 * AGG_MAX + COARSE_NT - 1) / COARSE_NT;
   const int t = threadIdx.x;
   double pv[NV][PW];
@@ -1035,14 +1034,14 @@ __device__ void coarse_space_correction(const CoarseArgs& A, int nwa, int win,
   __syncthreads();
 }
 
-// Dynamic LDS of the upper-level kernel: two windows of the set vectors, the
+// Dynamic LDS of the upper-level kernel: a window of the set vectors, the
 // own rows of the vector being preconditioned and the window aggregates'
 // rows of the coarse-space inverse, plus (when they fit) the own sets' PCG
 // vectors and their blocks.
 size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds, int two_level) {
   const size_t spw = (size_t)(g.M + nwg - 1) / nwg;
   const size_t win = std::min((size_t)g.M, spw + 2 * (size_t)g.mx + 2);
-  size_t b = (spw + 2 * win) * Q * sizeof(double);
+  size_t b = (spw + win) * Q * sizeof(double);
   if (two_level) {
     const AggLayout al = agg_layout(g.M, g.mx, nwg);
     b += (size_t)6 * al.nwa_max * 6 * al.naggr * sizeof(double);   // coarse-space rows
@@ -1086,8 +1085,10 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   const int wmax = min(M, spw + 2 * g.mx + 2);
   double* lown = lds;                          // own rows of the vector being preconditioned
   double* lw1 = lown + (size_t)spw * Q;        // window (first vector)
-  double* lw2 = lw1 + (size_t)wmax * Q;        // window (second vector)
-  double* lrows = lw2 + (size_t)wmax * Q;     // window aggregates' rows of A0^+
+  // The start's second window (u0) reuses the first: the first holds the
+  // previous coefficients only until the start's grid sum.
+  double* lw2 = lw1;
+  double* lrows = lw1 + (size_t)wmax * Q;     // window aggregates' rows of A0^+
   const AggLayout alay = agg_layout(M, g.mx, nwg);
   const size_t nrows_lds = two ? (size_t)6 * alay.nwa_max * 6 * alay.naggr : 0;
   double* ldxy = lrows + nrows_lds;                     // [wmax][3]: dx, dy, aggregate
@@ -1248,7 +1249,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   }
   __syncthreads();
   for (int e = t; e < nrow; e += COARSE_NT) {
-    vx[e] = theta * lw1[(size_t)(s0 - w0) * Q + e];
+    vx[e] = warm ? theta * A.a[r0 + e] : 0.0;
     vr[e] = A.force[r0 + e] - theta * vn[e];
     vu[e] = lw2[(size_t)(s0 - w0) * Q + e];     // M^-1 r0 on the own rows
   }
@@ -1361,6 +1362,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     // m = B^+ w published for the neighbours
     double gd[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double c6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
     for (int e = t; e < nrow; e += COARSE_NT) {
       const double u = vu[e], wv = vw[e];
       gd[0] += vr[e] * u;
@@ -1375,6 +1377,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     for (int k = 0; k < 6; ++k) gd[2 + k] = c6[k];
     __syncthreads();
     double* mpub = (it & 1) ? A.pub0 : A.pub2;
+#pragma unroll 4
     for (int e = t; e < nrow; e += COARSE_NT) {
       const double mv = pinv_row(bi, s0 + e / Q, s0, e % Q, lown);
       if (nwg == 1) lw1[e] = mv;            // one workgroup: the window is its own sets
@@ -1383,7 +1386,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     if (!grid_publish_wait<8>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
       return;
     // one round trip: the partial sums, the restrictions and the neighbours' m
-    grid_collect_window<2>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q, 2,
+    grid_collect_window<2, 1, 16>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q, 2,
                            two ? 1 : 0, A.agg_g, A.naggr, s_c);
     if (two && nwg == 1 && t < 6) s_c[t] = sv[2 + t];
     slot ^= 1;
@@ -1403,6 +1406,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     }
     if (!(alpha > 0.0)) break;
     if (two) coarse_space_correction(A, nwa, win, s_c, s_y, lw1, lrows, ldxy);
+#pragma unroll 2
     for (int e = t; e < nrow; e += COARSE_NT) {
       const double n = coarse_row(g, bd, ob, s0 + e / Q, s0, e % Q, lw1, w0);
       const double m = lw1[(size_t)(s0 - w0) * Q + e];
