@@ -93,7 +93,8 @@ typedef struct {
     tl_precision precision;
     double rtol;               /* stop when max(R1, R2) <= rtol (Eq. 19, both norms) */
     int32_t max_iters;         /* outer iterations; 0 = library default             */
-    int32_t inner_iters;       /* relaxation PCG sweeps per set; 0 = default (10)    */
+    int32_t inner_iters;       /* relaxation PCG sweeps per set; 0 = default (16, or
+                                  24 with 64 x 64 sets)                              */
     int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default (100)   */
     double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default 0.1 */
     int32_t warm_start;        /* 1: start from the free DOFs of u (else from 0)     */
