@@ -29,9 +29,12 @@ constexpr int NRM = 4;          // sum|r|, sum r^2, sum|f|, sum f^2 (free DOFs)
 constexpr int TILE_OUT = KROW + Q + NRM;
 constexpr int COARSE_NT = 256;  // threads per upper-level workgroup
 constexpr int COARSE_MAX_WG = 256;
+constexpr int BAR_GROUPS = 8;     // group counters of the grid barrier (one 64-byte line each)
+static_assert(BAR_GROUPS * 16 + 1 <= COARSE_MAX_WG, "barrier counters live in the flag array");
 constexpr int REDW = 24;        // values per workgroup and slot of a grid sum
 constexpr int AGG_MAX = 32;     // aggregates of the upper-level coarse space (at most)
 constexpr int AGG_GMAX = 8;     // workgroups per aggregate (at most: COARSE_MAX_WG / AGG_MAX)
+constexpr int AGG_PART = (COARSE_NT / 64) * 2 * 64;   // partial sums of the window solve (doubles)
 // Dynamic LDS of one upper-level workgroup, at most: the 160 KB of a CU less
 // the kernel's static arrays (grid-sum and coarse-space scratch, 7 KB).
 constexpr size_t COARSE_DYN_LDS_MAX = 152 * 1024;
@@ -122,8 +125,8 @@ struct CoarseArgs {
   double* pub0;          // [9M]
   double* pub1;          // [9M]
   double* pub2;          // [9M]
-  double* red;           // [2][COARSE_MAX_WG][REDW] reduction slots
-  unsigned* flags;       // [COARSE_MAX_WG] arrival generations of the grid sums
+  double* red;           // [2][REDW][COARSE_MAX_WG] reduction slots (value-major)
+  unsigned* flags;       // [COARSE_MAX_WG] grid-barrier counters: group g at [16 g], root at [16 BAR_GROUPS]
   double* hist;          // [max_iters + 1] max(R1, R2) per outer iteration (may be null)
   double* tr_kdiag;      // optional copies of the solved system (diagnostics)
   double* tr_koff;

@@ -777,14 +777,14 @@ __device__ __forceinline__ double pub_load(const double* p) {
 // Grid-wide sum of up to REDW values, which is also the grid barrier.
 // Workgroup w publishes its partials in slot `slot`, waits for all of its
 // stores (the partials and any values published before the call), then
-// raises flags[w] to `gen`; every workgroup waits until all flags have
-// reached `gen` and adds the partials in workgroup order, so all threads of
-// all workgroups get the same bits.  No counter is shared, so arrivals do not
-// serialise on one address.  A workgroup can run at most one sum ahead of the
-// slowest, hence two slots and the wrap-safe ">= gen" test.  Bounded: after
-// spin_limit polls the error flag is raised and every later call returns
-// false at once, so the grid always drains.  With one workgroup the partials
-// are left in sv and no memory round trip is made.
+// arrives on a two-level counter (eight group counters, then a root); every
+// workgroup waits until the root shows all arrivals of generation `gen` and
+// then adds the partials in workgroup order, so all threads of all
+// workgroups get the same bits.  A workgroup can run at most one sum ahead of
+// the slowest, hence two slots.  Bounded: after spin_limit polls the error
+// flag is raised and every later call returns false at once, so the grid
+// always drains.  With one workgroup the partials are left in sv and no
+// memory round trip is made.
 template <int NV>
 __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* flags,
                                   unsigned gen, int slot, Ctrl* c, int wid, int nwg,
@@ -804,7 +804,7 @@ __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* 
 #pragma unroll
     for (int w = 0; w < COARSE_NT / 64; ++w) bs += wsum[threadIdx.x][w];
     if (nwg == 1) sv[threadIdx.x] = bs;
-    else pub_store(&red[((size_t)slot * COARSE_MAX_WG + wid) * REDW + threadIdx.x], bs);
+    else pub_store(&red[((size_t)slot * REDW + threadIdx.x) * COARSE_MAX_WG + wid], bs);
   }
   if (nwg == 1) {
     __syncthreads();
@@ -813,112 +813,130 @@ __device__ bool grid_publish_wait(const double (&v)[NV], double* red, unsigned* 
   // one wait covers every store of this workgroup: published values and partials
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x < 64) {
-    int good = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-    if (threadIdx.x == 0 && good)
-      __hip_atomic_store(&flags[wid], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    // Arrival: one atomic add on the counter of the workgroup's group (the
+    // workgroups w with the same w mod 8); the group's last arrival adds one
+    // to the root counter, which every workgroup polls.  The counters only
+    // grow from zero (they are cleared with the solve's state), so after
+    // grid sum number gen the root holds gen times the number of groups.
+    const int grp = wid % BAR_GROUPS;
+    const int gsize = nwg / BAR_GROUPS + (grp < nwg % BAR_GROUPS ? 1 : 0);
+    const unsigned ngrp = (unsigned)min(nwg, BAR_GROUPS);
+    unsigned* root = flags + BAR_GROUPS * 16;
+    const unsigned old = __hip_atomic_fetch_add(flags + grp * 16, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if ((old + 1u) % (unsigned)gsize == 0u)
+      __hip_atomic_fetch_add(root, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = gen * ngrp;
+    int good = 1;
     unsigned n = 0;
-    while (good) {
-      bool mine = true;
-      for (int w = threadIdx.x; w < nwg; w += 64)
-        mine &= (int)(__hip_atomic_load(&flags[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - gen) >= 0;
-      if (__all(mine)) break;
-      if (++n > spin || __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        if (threadIdx.x == 0) __hip_atomic_store(&c->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+      // the root and the error flag are loaded together: one round trip a poll
+      const unsigned rv = __hip_atomic_load(root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int err = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const bool done = (int)(rv - target) >= 0;
+      if (err != 0 || (!done && ++n > spin)) {
+        __hip_atomic_store(&c->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         good = 0;
         break;
       }
+      if (done) break;
       __builtin_amdgcn_s_sleep(1);
     }
-    if (threadIdx.x == 0) ok = good;
+    ok = good;
   }
   __syncthreads();
   (void)sslot;
   return ok != 0;
 }
 
-// After a grid sum: add the published partials into sv (one wave; lane l
-// takes workgroups l, l + 64, ... in order, then a butterfly, the same tree
-// in every workgroup, so every workgroup gets the same bits), copy the
+// After a grid sum: add the published partials into sv, copy the
 // neighbours' published window values into LDS, and (agg_nvec > 0) gather
 // the coarse-space restrictions: for each of agg_nvec vectors, entry
 // (aggregate a, mode k) is the sum, in workgroup order, of partial
-// agg_k0 + 6 v + k of the agg_g workgroups of aggregate a.  All loads are
-// issued before any is used, so they take one memory round trip together.
-// Only the collecting threads write sv / s_c; the caller synchronises.
+// agg_k0 + 6 v + k of the agg_g workgroups of aggregate a.  The partials are
+// stored value-major ([slot][value][workgroup]) so that these loads are
+// contiguous across lanes.  Thread t takes workgroup t's partials; the four
+// waves' sums are added in wave order, the same tree in every workgroup, so
+// every workgroup gets the same bits.  All loads are issued before any is
+// used, so they take one memory round trip together.  Only the collecting
+// threads write sv / s_c; the caller synchronises.
 template <int NV, int NVEC = 1, int WB = 4>
 __device__ void grid_collect_window(const double* red, int slot, int nwg, double* sv,
                                     double* dst, const double* src, int n,
                                     int agg_k0 = 0, int agg_nvec = 0, int agg_g = 1,
                                     int naggr = 0, double* s_c = nullptr) {
-  constexpr int PW = COARSE_MAX_WG / 64;
+  constexpr int NWV = COARSE_NT / 64;
   constexpr int CB = (NVEC * 6 * AGG_MAX + COARSE_NT - 1) / COARSE_NT;
-  const int t = threadIdx.x;
-  double pv[NV][PW];
-  if (nwg > 1 && t < 64) {
+  static_assert(COARSE_NT == COARSE_MAX_WG, "one collecting thread per workgroup");
+  __shared__ double wpart[NV][NWV];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  if (nwg <= 1) return;
+  const double* rs = red + (size_t)slot * REDW * COARSE_MAX_WG;
+  // Every load is issued unconditionally, with its index clamped into the
+  // buffer, and what a lane does not need is dropped by a select later.  A
+  // load under a branch lets the compiler pull its first use next to it,
+  // which costs one memory round trip per load; this way all of them are in
+  // flight together.
+  double pv[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-      for (int j = 0; j < PW; ++j) {
-        const int w = t + 64 * j;
-        pv[k][j] = w < nwg ? pub_load(&red[((size_t)slot * COARSE_MAX_WG + w) * REDW + k]) : 0.0;
-      }
-  }
-  // coarse-space restrictions: entries t, t + NT of the agg_nvec * 6 * naggr
+  for (int k = 0; k < NV; ++k) pv[k] = pub_load(&rs[(size_t)k * COARSE_MAX_WG + t]);
+  // coarse-space restrictions: entry e = (6 v + k) naggr + a, for e = t, t + NT
   double cv[CB][AGG_GMAX];
   const int ctot = agg_nvec * 6 * naggr;
+  const int na = max(naggr, 1);
 #pragma unroll
   for (int b = 0; b < CB; ++b) {
-    const int e = t + b * COARSE_NT;
-    const int v = e / (6 * max(naggr, 1)), idx = e - v * 6 * max(naggr, 1);
-    const int ag = idx / 6, k = idx - 6 * ag;
+    const int e = t + b * COARSE_NT < ctot ? t + b * COARSE_NT : 0;
+    const int vk = e / na, ag = e - vk * na;
+    const double* col = rs + (size_t)(agg_k0 + vk) * COARSE_MAX_WG;
 #pragma unroll
-    for (int j = 0; j < AGG_GMAX; ++j) {
-      const int w = ag * agg_g + j;
-      cv[b][j] = (e < ctot && j < agg_g && w < nwg)
-                     ? (nwg > 1 ? pub_load(&red[((size_t)slot * COARSE_MAX_WG + w) * REDW + agg_k0 + 6 * v + k])
-                                : 0.0)
-                     : 0.0;
-    }
+    for (int j = 0; j < AGG_GMAX; ++j) cv[b][j] = pub_load(&col[min(ag * agg_g + j, COARSE_MAX_WG - 1)]);
   }
-  if (nwg > 1 && src) {
-    for (int base = 0; base < n; base += WB * COARSE_NT) {
-      double wv[WB];
+  // the window: its first WB * NT entries (normally all of it) are loaded
+  // here, outside any loop, so that they share the round trip above
+  const bool win_on = src != nullptr && n > 0;
+  double wv_[WB];
+  if (win_on) {
+#pragma unroll
+    for (int b = 0; b < WB; ++b) wv_[b] = pub_load(&src[min(t + b * COARSE_NT, n - 1)]);
+  }
+  if (win_on) {
+#pragma unroll
+    for (int b = 0; b < WB; ++b)
+      if (t + b * COARSE_NT < n) dst[t + b * COARSE_NT] = wv_[b];
+    for (int base = WB * COARSE_NT; base < n; base += WB * COARSE_NT) {
+#pragma unroll
+      for (int b = 0; b < WB; ++b) wv_[b] = pub_load(&src[min(base + t + b * COARSE_NT, n - 1)]);
 #pragma unroll
       for (int b = 0; b < WB; ++b) {
         const int e = base + t + b * COARSE_NT;
-        wv[b] = e < n ? pub_load(&src[e]) : 0.0;
-      }
-#pragma unroll
-      for (int b = 0; b < WB; ++b) {
-        const int e = base + t + b * COARSE_NT;
-        if (e < n) dst[e] = wv[b];
+        if (e < n) dst[e] = wv_[b];
       }
     }
   }
-  if (nwg > 1 && t < 64) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double sum = 0.0;
-#pragma unroll
-      for (int j = 0; j < PW; ++j)
-        if (t + 64 * j < nwg) sum += pv[k][j];
-      sum = wave_sum(sum);
-      if (t == 0) sv[k] = sum;
-    }
+  for (int k = 0; k < NV; ++k) {
+    const double x = wave_sum(t < nwg ? pv[k] : 0.0);
+    if (lane == 0) wpart[k][wv] = x;
   }
-  if (nwg > 1) {
+  if (ctot > 0) {
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
       const int e = t + b * COARSE_NT;
-      if (e < ctot) {
-        double sum = 0.0;
+      const int vk = e / na, ag = e - vk * na;
+      double sum = 0.0;
 #pragma unroll
-        for (int j = 0; j < AGG_GMAX; ++j) sum += cv[b][j];
-        const int v = e / (6 * naggr);
-        s_c[v * 6 * AGG_MAX + (e - v * 6 * naggr)] = sum;
-      }
+      for (int j = 0; j < AGG_GMAX; ++j) sum += j < agg_g && ag * agg_g + j < nwg ? cv[b][j] : 0.0;
+      if (e < ctot) s_c[(vk / 6) * 6 * AGG_MAX + 6 * ag + vk % 6] = sum;
     }
+  }
+  __syncthreads();
+  if (t < NV) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < NWV; ++q) sum += wpart[t][q];
+    sv[t] = sum;
   }
 }
 
@@ -964,20 +982,58 @@ __device__ __forceinline__ double agg_prolong(int l, const double* y, double dx,
 }
 
 // y[v][r] = (A0^+ c[v]) on the rows r = 6 (a - a_lo) + k of the aggregates
-// a_lo .. a_lo + nwa - 1, whose rows of A0^+ are `rows` (in LDS): one wave
-// per row, lanes across the columns.
-__device__ void agg_window_solve(const double* rows, int naggr, int nwa, const double* c,
-                                 double* y, int nvec) {
-  const int n = 6 * naggr;
+// a_lo .. a_lo + nwa - 1.  Their rows of A0^+ are in LDS column by column
+// (entry (r, j) at rows[j * 6 nwa + r]).  Each lane takes a row and a run of
+// columns: with at most 16 (32) rows in any window of the lattice (nr_max)
+// a wave holds four (two) runs side by side, and the four waves take
+// further runs, so no lane waits on a cross-lane sum.  The runs meet in
+// `part` ([runs][2][rows per pass]) and are added in run order; the runs
+// depend only on the lattice, so every workgroup gets the same bits for a
+// shared aggregate.  Ends synchronised.
+constexpr int SOLVE_STEP = 6;
+__device__ void agg_window_solve(const double* rows, int naggr, int nwa, int nr_max,
+                                 const double* c, double* y, int nvec, double* part) {
+  constexpr int NWV = COARSE_NT / 64;
+  const int n = 6 * naggr, nr = 6 * nwa;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int r = wv; r < 6 * nwa; r += COARSE_NT / 64) {
-    const double* row = rows + (size_t)r * n;
+  const int PH = nr_max <= 16 ? 4 : nr_max <= 32 ? 2 : 1;
+  const int RP = 64 / PH;                   // rows per pass
+  const int ph = lane / RP, rl = lane - RP * ph;
+  const int nq = NWV * PH, q = wv * PH + ph;
+  const int cq = (n + nq - 1) / nq;
+  const int jb = min(n, q * cq), je = min(n, jb + cq);
+  for (int rb = 0; rb < nr; rb += RP) {
+    const int r = min(rb + rl, nr - 1);
     for (int v = 0; v < nvec; ++v) {
-      double sum = 0.0;
-      for (int j = lane; j < n; j += 64) sum += row[j] * c[v * 6 * AGG_MAX + j];
-      sum = wave_sum(sum);
-      if (lane == 0) y[v * 6 * AGG_MAX + r] = sum;
+      const double* cv = c + v * 6 * AGG_MAX;
+      // SOLVE_STEP columns per step, all loads issued before any product
+      // (the step is bound by LDS latency); past je the column index is
+      // clamped and the factor is zero
+      double acc[2] = {0.0, 0.0};
+      for (int j0 = jb; j0 < je; j0 += SOLVE_STEP) {
+        double rv[SOLVE_STEP], cc[SOLVE_STEP];
+#pragma unroll
+        for (int k = 0; k < SOLVE_STEP; ++k) {
+          const int j = min(j0 + k, je - 1);
+          rv[k] = rows[(size_t)j * nr + r];
+          const double cj = cv[j];
+          cc[k] = j0 + k < je ? cj : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < SOLVE_STEP; ++k) acc[k & 1] += rv[k] * cc[k];
+      }
+      part[(q * 2 + v) * RP + rl] = acc[0] + acc[1];
     }
+    __syncthreads();
+    if ((int)threadIdx.x < RP * nvec) {
+      const int v = threadIdx.x / RP, l = threadIdx.x - RP * v;
+      if (rb + l < nr) {
+        double sum = 0.0;
+        for (int qq = 0; qq < nq; ++qq) sum += part[(qq * 2 + v) * RP + l];
+        y[v * 6 * AGG_MAX + rb + l] = sum;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1022,14 +1078,17 @@ __device__ __forceinline__ double pinv_row(const double* bi, int s, int s0, int 
 // the window copy of m (modes 1-6).  Ends synchronised.
 __device__ void coarse_space_correction(const CoarseArgs& A, int nwa, int win,
                                         const double* s_c, double* s_y, double* lw,
-                                        const double* lrows, const double* ldxy) {
-  agg_window_solve(lrows, A.naggr, nwa, s_c, s_y, 1);
-  __syncthreads();
-  for (int e = threadIdx.x; e < win * Q; e += COARSE_NT) {
-    const int sl = e / Q, l = e - Q * sl;
-    if (l >= 6) continue;
+                                        const double* lrows, const double* ldxy,
+                                        double* lpart, int nr_max) {
+  agg_window_solve(lrows, A.naggr, nwa, nr_max, s_c, s_y, 1, lpart);
+  // one thread per window set: its aggregate's six values, then modes 1-6
+  for (int sl = threadIdx.x; sl < win; sl += COARSE_NT) {
     const double* d = ldxy + 3 * sl;
-    lw[e] += agg_prolong(l, s_y + 6 * (int)d[2], d[0], d[1]);
+    const double dx = d[0], dy = d[1];
+    const double* y = s_y + 6 * (int)d[2];
+    double* m = lw + (size_t)sl * Q;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) m[l] += agg_prolong(l, y, dx, dy);
   }
   __syncthreads();
 }
@@ -1046,6 +1105,7 @@ size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds, int two
     const AggLayout al = agg_layout(g.M, g.mx, nwg);
     b += (size_t)6 * al.nwa_max * 6 * al.naggr * sizeof(double);   // coarse-space rows
     b += 3 * win * sizeof(double);                                  // P0 entries of the window
+    b += AGG_PART * sizeof(double);                                 // partial sums of its solve
   }
   if (vec_lds) b += 8 * spw * Q * sizeof(double);
   if (blk_lds) b += spw * (NDIR + 2) * Q * Q * sizeof(double);
@@ -1092,7 +1152,8 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   const AggLayout alay = agg_layout(M, g.mx, nwg);
   const size_t nrows_lds = two ? (size_t)6 * alay.nwa_max * 6 * alay.naggr : 0;
   double* ldxy = lrows + nrows_lds;                     // [wmax][3]: dx, dy, aggregate
-  double* lnext = ldxy + (two ? (size_t)3 * wmax : 0);
+  double* lpart = ldxy + (two ? (size_t)3 * wmax : 0);  // [4][2][64] partial sums of the solve
+  double* lnext = lpart + (two ? (size_t)AGG_PART : 0);
   const size_t r0 = (size_t)s0 * Q;            // first own row
   // Own-row vectors, touched only by the owning thread: in LDS when they fit,
   // else in global memory.  All are indexed from the workgroup's first row.
@@ -1128,7 +1189,8 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
 
   if (two) {   // the window aggregates' rows of A0^+ and P0's entries, once per launch
     const int n = 6 * A.naggr;
-    for (int e = t; e < 6 * nwa * n; e += COARSE_NT) lrows[e] = A.agg_inv[(size_t)6 * a_lo * n + e];
+    for (int e = t; e < 6 * nwa * n; e += COARSE_NT)      // stored column by column
+      lrows[(size_t)(e % n) * 6 * nwa + e / n] = A.agg_inv[(size_t)6 * a_lo * n + e];
     for (int e = t; e < win; e += COARSE_NT) {
       double dx, dy;
       agg_coef(g, A.agg_xy, A.agg_sets, w0 + e, dx, dy);
@@ -1230,22 +1292,36 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   const double theta = (warm && red6[5] > 0.0 && red6[4] > 0.0) ? red6[4] / red6[5] : 0.0;
   // coarse-space parts of B^+ P and B^+ y on the window's aggregates
   if (two) {
-    agg_window_solve(lrows, A.naggr, nwa, s_c, s_y, 2);
-    __syncthreads();
+    agg_window_solve(lrows, A.naggr, nwa, 6 * alay.nwa_max, s_c, s_y, 2, lpart);
   }
   // x0, r0, u0 (own) and u0 over the window, then w0 = K_a u0
-  for (int e = t; e < win * Q; e += COARSE_NT) {
-    const size_t ge = (size_t)w0 * Q + e;
-    double v = pub_load(&A.pub0[ge]) - theta * pub_load(&A.pub1[ge]);
-    if (two && e % Q < 6) {
-      const double* d = ldxy + 3 * (e / Q);
-      const int al = (int)d[2];
-      double yv[6];
+  // (the published values are loaded four rows per thread at a time, so
+  // that their round trips overlap)
+  for (int base = 0; base < win * Q; base += 4 * COARSE_NT) {
+    double p0[4], p1[4];
+    const double* g0 = A.pub0 + (size_t)w0 * Q;
+    const double* g1 = A.pub1 + (size_t)w0 * Q;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) yv[k] = s_y[6 * al + k] - theta * s_y[6 * AGG_MAX + 6 * al + k];
-      v += agg_prolong(e % Q, yv, d[0], d[1]);
+    for (int c = 0; c < 4; ++c) {
+      const int e = min(base + t + c * COARSE_NT, win * Q - 1);
+      p0[c] = pub_load(&g0[e]);
+      p1[c] = pub_load(&g1[e]);
     }
-    lw2[e] = v;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int e = base + t + c * COARSE_NT;
+      if (e >= win * Q) continue;
+      double v = p0[c] - theta * p1[c];
+      if (two && e % Q < 6) {
+        const double* d = ldxy + 3 * (e / Q);
+        const int al = (int)d[2];
+        double yv[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) yv[k] = s_y[6 * al + k] - theta * s_y[6 * AGG_MAX + 6 * al + k];
+        v += agg_prolong(e % Q, yv, d[0], d[1]);
+      }
+      lw2[e] = v;
+    }
   }
   __syncthreads();
   for (int e = t; e < nrow; e += COARSE_NT) {
@@ -1315,7 +1391,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
       }
       if (!grid_publish_wait<8>(gd, A.red, A.flags, base + (++nsync), slot, ctrl, w, nwg, spin, sslot, sv))
         return;
-      grid_collect_window<2>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q, 2,
+      grid_collect_window<2, 1, 4>(A.red, slot, nwg, sv, lw1, mpub + (size_t)w0 * Q, win * Q, 2,
                              two ? 1 : 0, A.agg_g, A.naggr, s_c);
       if (two && nwg == 1 && t < 6) s_c[t] = sv[2 + t];
       slot ^= 1;
@@ -1334,7 +1410,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
         alpha = den > 0.0 ? gamma / den : 0.0;
       }
       if (!(alpha > 0.0)) break;
-      if (two) coarse_space_correction(A, nwa, win, s_c, s_y, lw1, lrows, ldxy);
+      if (two) coarse_space_correction(A, nwa, win, s_c, s_y, lw1, lrows, ldxy, lpart, 6 * alay.nwa_max);
       double n = 0.0;
 #pragma unroll
       for (int l = 0; l < Q; ++l) n += brow[l] * lw1[sown + l];
@@ -1405,7 +1481,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
       alpha = den > 0.0 ? gamma / den : 0.0;
     }
     if (!(alpha > 0.0)) break;
-    if (two) coarse_space_correction(A, nwa, win, s_c, s_y, lw1, lrows, ldxy);
+    if (two) coarse_space_correction(A, nwa, win, s_c, s_y, lw1, lrows, ldxy, lpart, 6 * alay.nwa_max);
 #pragma unroll 2
     for (int e = t; e < nrow; e += COARSE_NT) {
       const double n = coarse_row(g, bd, ob, s0 + e / Q, s0, e % Q, lw1, w0);
