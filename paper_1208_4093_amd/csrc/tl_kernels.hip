@@ -1028,8 +1028,16 @@ __device__ void agg_window_solve(const double* rows, int naggr, int nwa, int nr_
     if ((int)threadIdx.x < RP * nvec) {
       const int v = threadIdx.x / RP, l = threadIdx.x - RP * v;
       if (rb + l < nr) {
+        // the runs' partials, four loads in flight at a time
         double sum = 0.0;
-        for (int qq = 0; qq < nq; ++qq) sum += part[(qq * 2 + v) * RP + l];
+        for (int q0 = 0; q0 < nq; q0 += 4) {
+          double pr[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) pr[k] = part[(min(q0 + k, nq - 1) * 2 + v) * RP + l];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (q0 + k < nq) sum += pr[k];
+        }
         y[v * 6 * AGG_MAX + rb + l] = sum;
       }
     }
@@ -1112,6 +1120,64 @@ size_t coarse_lds_bytes(const Geo& g, int nwg, int vec_lds, int blk_lds, int two
   return b;
 }
 
+// A plain load that the compiler keeps where it is written: a relaxed
+// atomic load at workgroup scope is an ordinary cached load, but it is not
+// moved next to its first use, so a batch of them shares one round trip.
+__device__ __forceinline__ double stage_load(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// n doubles from global memory into LDS, LDS_COPY_BATCH loads in flight per
+// thread (a copy loop with one load per step waits a full memory round trip
+// per step).
+constexpr int LDS_COPY_BATCH = 16;
+__device__ __forceinline__ void copy_to_lds(double* dst, const double* src, int n) {
+  const int t = threadIdx.x;
+  for (int base = 0; base < n; base += LDS_COPY_BATCH * COARSE_NT) {
+    double v[LDS_COPY_BATCH];
+#pragma unroll
+    for (int b = 0; b < LDS_COPY_BATCH; ++b) v[b] = stage_load(&src[min(base + t + b * COARSE_NT, n - 1)]);
+#pragma unroll
+    for (int b = 0; b < LDS_COPY_BATCH; ++b)
+      if (base + t + b * COARSE_NT < n) dst[base + t + b * COARSE_NT] = v[b];
+  }
+}
+
+// Four copies from global memory into LDS as one index space, so that the
+// loads of all of them are in flight together: segments 0-2 are plain
+// copies, segment 3 is stored transposed (element e of a block with tn
+// columns goes to (e mod tn) * tr + e / tn).  A segment with n = 0 is
+// skipped.
+constexpr int LDS_STAGE_BATCH = 32;
+__device__ __forceinline__ void stage_to_lds(double* d0, const double* s0, int n0, double* d1,
+                                             const double* s1, int n1, double* d2,
+                                             const double* s2, int n2, double* d3,
+                                             const double* s3, int n3, int tn, int tr) {
+  const int t = threadIdx.x;
+  const int c1 = n0, c2 = n0 + n1, c3 = n0 + n1 + n2, N = c3 + n3;
+  for (int base = 0; base < N; base += LDS_STAGE_BATCH * COARSE_NT) {
+    double v[LDS_STAGE_BATCH];
+#pragma unroll
+    for (int b = 0; b < LDS_STAGE_BATCH; ++b) {
+      const int e = min(base + t + b * COARSE_NT, N - 1);
+      const double* p = e < c1 ? s0 + e : e < c2 ? s1 + (e - c1) : e < c3 ? s2 + (e - c2) : s3 + (e - c3);
+      v[b] = stage_load(p);
+    }
+#pragma unroll
+    for (int b = 0; b < LDS_STAGE_BATCH; ++b) {
+      const int e = base + t + b * COARSE_NT;
+      if (e >= N) continue;
+      if (e < c1) d0[e] = v[b];
+      else if (e < c2) d1[e - c1] = v[b];
+      else if (e < c3) d2[e - c2] = v[b];
+      else {
+        const int k = e - c3;
+        d3[(size_t)(k % tn) * tr + k / tn] = v[b];
+      }
+    }
+  }
+}
+
 // Upper-level kernel.  Pipelined block-Jacobi PCG (the Ghysels-Vanroose
 // recurrences): per iteration one grid sum carries both dot products and
 // orders the publication of m = B^+ w, whose neighbour values the product
@@ -1122,7 +1188,11 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   __shared__ double sslot[COARSE_NT / 64];
   __shared__ double sv[REDW];
   Ctrl* ctrl = A.ctrl;
-  if (ctrl->done) return;
+  // the control words are read together (one round trip), then tested
+  const int done = __hip_atomic_load(&ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const unsigned base = __hip_atomic_load(&ctrl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int iter = __hip_atomic_load(&ctrl->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (done) return;
   const int t = threadIdx.x;
   const int M = g.M;
   const int spw = (M + nwg - 1) / nwg;
@@ -1138,8 +1208,6 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   __shared__ double s_y[2 * 6 * AGG_MAX];
   const int a_lo = two && win > 0 ? w0 / A.agg_sets : 0;
   const int nwa = two && win > 0 ? (w1 - 1) / A.agg_sets - a_lo + 1 : 0;
-  const unsigned base = ctrl->bar_gen;
-  const int iter = ctrl->k;
   unsigned nsync = 0;
   int slot = 0;
   const int wmax = min(M, spw + 2 * g.mx + 2);
@@ -1173,24 +1241,24 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   const double* bd = A.bdiag + (size_t)s0 * Q * Q;
   const double* ob = A.off + (size_t)s0 * NDIR * Q * Q;
   const double* bi = A.binv + (size_t)s0 * Q * Q;
-  if (A.blk_lds) {
+  // Staged into LDS once per launch, all in one stream of loads: the own
+  // sets' blocks (when they fit) and the window aggregates' rows of A0^+
+  // (column by column).
+  {
+    const int nb = A.blk_lds ? ns * Q * Q : 0, no = A.blk_lds ? ns * NDIR * Q * Q : 0;
+    const int nrw = two ? 6 * nwa * 6 * A.naggr : 0;
     double* lb = lnext;
-    for (int e = t; e < ns * Q * Q; e += COARSE_NT) {
-      lb[e] = bd[e];
-      lb[(size_t)spw * Q * Q + e] = bi[e];
+    stage_to_lds(lb, bd, nb, lb + (size_t)spw * Q * Q, bi, nb, lb + 2 * (size_t)spw * Q * Q, ob, no,
+                 lrows, two ? A.agg_inv + (size_t)36 * a_lo * A.naggr : nullptr, nrw,
+                 6 * A.naggr, 6 * nwa);
+    if (A.blk_lds) {
+      bd = lb;
+      bi = lb + (size_t)spw * Q * Q;
+      ob = lb + 2 * (size_t)spw * Q * Q;
     }
-    double* lo = lb + 2 * (size_t)spw * Q * Q;
-    for (int e = t; e < ns * NDIR * Q * Q; e += COARSE_NT) lo[e] = ob[e];
-    bd = lb;
-    bi = lb + (size_t)spw * Q * Q;
-    ob = lo;
     __syncthreads();
   }
-
-  if (two) {   // the window aggregates' rows of A0^+ and P0's entries, once per launch
-    const int n = 6 * A.naggr;
-    for (int e = t; e < 6 * nwa * n; e += COARSE_NT)      // stored column by column
-      lrows[(size_t)(e % n) * 6 * nwa + e / n] = A.agg_inv[(size_t)6 * a_lo * n + e];
+  if (two) {   // P0's entries of the window, once per launch
     for (int e = t; e < win; e += COARSE_NT) {
       double dx, dy;
       agg_coef(g, A.agg_xy, A.agg_sets, w0 + e, dx, dy);
@@ -1209,7 +1277,9 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   //     two dot products, the stop test's four norm sums, and orders the
   //     publication of B^+ P and B^+ y.
   const bool warm = A.warm && iter > 0;
-  for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = warm ? A.a[(size_t)w0 * Q + e] : 0.0;
+  if (warm) copy_to_lds(lw1, A.a + (size_t)w0 * Q, win * Q);
+  else
+    for (int e = t; e < win * Q; e += COARSE_NT) lw1[e] = 0.0;
   __syncthreads();
   // [0..3] stop-test norms, [4..5] theta's dot products, [6] P . B^+ P,
   // [7..12] P0^T P, [13..18] P0^T y (coarse space)
