@@ -216,6 +216,10 @@ def run_single(args, wl):
             "kernel_share": {k: v / max(sum(kern.values()), 1e-30) for k, v in kern.items()},
             "tile_gbs": tile_gbs,
             "tile_bytes_per_launch": tile_bytes_per_node(mixed) * nodes,
+            # the upper-level kernel is bound by its grid synchronisations: time
+            # per PCG iteration (launch prologue included)
+            "coarse_us_per_pcg_iteration": 1000.0 * kern["coarse"]
+                                           / max(sum(i["coarse_iters"] for i in infos), 1),
         }
 
     forms = [tl.TL_FP64, tl.TL_MIXED] if wl["headline"] == "fp64" else [tl.TL_MIXED, tl.TL_FP64]
@@ -248,6 +252,8 @@ def run_single(args, wl):
         "coarse_iters": head["coarse_iters"],
         "rel_res": head["rel_res"],
         "kernel_ms_per_launch": head["kernel_ms_per_launch"],
+        "kernel_share": head["kernel_share"],
+        "coarse_us_per_pcg_iteration": head["coarse_us_per_pcg_iteration"],
     })
     if len(forms) > 1:
         other = res[forms[1]]
