@@ -50,16 +50,43 @@ __device__ __forceinline__ void set_coords(int i, int j, int i0, int j0, int tw,
   eta = ((j - jc) * kS3) * inv_hs;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Wave sums with DPP lane moves (VALU operand modifiers, no LDS traffic):
+// two quad exchanges, the half-row and row mirrors give every lane its
+// 16-lane row sum, then the two row broadcasts carry the row sums to lane 63,
+// whose value every lane reads.  All 64 lanes must be active (every call
+// site is workgroup-uniform and every block is a whole number of waves).
+// The order of the additions is fixed, so every wave adds the same way.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
 }
+__device__ __forceinline__ double lane63(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T v) {
+  v += dpp_move<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);        // row_half_mirror
+  v += dpp_move<0x140>(v);        // row_mirror
+  v += dpp_move<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return lane63(v);
+}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
+__device__ __forceinline__ float wave_sum(float v) { return wave_sum_dpp(v); }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
