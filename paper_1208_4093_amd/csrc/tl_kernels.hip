@@ -87,10 +87,22 @@ __device__ __forceinline__ T wave_sum_dpp(T v) {
 }
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 __device__ __forceinline__ float wave_sum(float v) { return wave_sum_dpp(v); }
+// Wave maximum, same lane moves; rows a broadcast skips keep their own value.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_move_keep(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_move_keep<0xB1>(v));
+  v = fmax(v, dpp_move_keep<0x4E>(v));
+  v = fmax(v, dpp_move_keep<0x141>(v));
+  v = fmax(v, dpp_move_keep<0x140>(v));
+  v = fmax(v, dpp_move_keep<0x142, 0xA>(v));
+  v = fmax(v, dpp_move_keep<0x143, 0xC>(v));
+  return lane63(v);
 }
 
 // Wave sums of V values at once (V a power of two, at most 64) with about V
