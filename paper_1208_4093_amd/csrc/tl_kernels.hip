@@ -1182,37 +1182,19 @@ __device__ __forceinline__ void copy_to_lds(double* dst, const double* src, int 
   }
 }
 
-// Four copies from global memory into LDS as one index space, so that the
-// loads of all of them are in flight together: segments 0-2 are plain
-// copies, segment 3 is stored transposed (element e of a block with tn
-// columns goes to (e mod tn) * tr + e / tn).  A segment with n = 0 is
-// skipped.
-constexpr int LDS_STAGE_BATCH = 32;
-__device__ __forceinline__ void stage_to_lds(double* d0, const double* s0, int n0, double* d1,
-                                             const double* s1, int n1, double* d2,
-                                             const double* s2, int n2, double* d3,
-                                             const double* s3, int n3, int tn, int tr) {
-  const int t = threadIdx.x;
-  const int c1 = n0, c2 = n0 + n1, c3 = n0 + n1 + n2, N = c3 + n3;
-  for (int base = 0; base < N; base += LDS_STAGE_BATCH * COARSE_NT) {
-    double v[LDS_STAGE_BATCH];
+// An r x n row-major block from global memory into LDS column by column
+// (element (i, j) to dst[j * r + i]), LDS_COPY_BATCH loads in flight per
+// thread.
+__device__ __forceinline__ void copy_to_lds_transposed(double* dst, const double* src, int r, int n) {
+  const int t = threadIdx.x, tot = r * n;
+  for (int base = 0; base < tot; base += LDS_COPY_BATCH * COARSE_NT) {
+    double v[LDS_COPY_BATCH];
 #pragma unroll
-    for (int b = 0; b < LDS_STAGE_BATCH; ++b) {
-      const int e = min(base + t + b * COARSE_NT, N - 1);
-      const double* p = e < c1 ? s0 + e : e < c2 ? s1 + (e - c1) : e < c3 ? s2 + (e - c2) : s3 + (e - c3);
-      v[b] = stage_load(p);
-    }
+    for (int b = 0; b < LDS_COPY_BATCH; ++b) v[b] = stage_load(&src[min(base + t + b * COARSE_NT, tot - 1)]);
 #pragma unroll
-    for (int b = 0; b < LDS_STAGE_BATCH; ++b) {
+    for (int b = 0; b < LDS_COPY_BATCH; ++b) {
       const int e = base + t + b * COARSE_NT;
-      if (e >= N) continue;
-      if (e < c1) d0[e] = v[b];
-      else if (e < c2) d1[e - c1] = v[b];
-      else if (e < c3) d2[e - c2] = v[b];
-      else {
-        const int k = e - c3;
-        d3[(size_t)(k % tn) * tr + k / tn] = v[b];
-      }
+      if (e < tot) dst[(size_t)(e % n) * r + e / n] = v[b];
     }
   }
 }
@@ -1280,23 +1262,20 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   const double* bd = A.bdiag + (size_t)s0 * Q * Q;
   const double* ob = A.off + (size_t)s0 * NDIR * Q * Q;
   const double* bi = A.binv + (size_t)s0 * Q * Q;
-  // Staged into LDS once per launch, all in one stream of loads: the own
-  // sets' blocks (when they fit) and the window aggregates' rows of A0^+
-  // (column by column).
-  {
-    const int nb = A.blk_lds ? ns * Q * Q : 0, no = A.blk_lds ? ns * NDIR * Q * Q : 0;
-    const int nrw = two ? 6 * nwa * 6 * A.naggr : 0;
+  // Staged into LDS once per launch: the own sets' blocks (when they fit)
+  // and the window aggregates' rows of A0^+ (column by column).
+  if (A.blk_lds) {
     double* lb = lnext;
-    stage_to_lds(lb, bd, nb, lb + (size_t)spw * Q * Q, bi, nb, lb + 2 * (size_t)spw * Q * Q, ob, no,
-                 lrows, two ? A.agg_inv + (size_t)36 * a_lo * A.naggr : nullptr, nrw,
-                 6 * A.naggr, 6 * nwa);
-    if (A.blk_lds) {
-      bd = lb;
-      bi = lb + (size_t)spw * Q * Q;
-      ob = lb + 2 * (size_t)spw * Q * Q;
-    }
-    __syncthreads();
+    copy_to_lds(lb, bd, ns * Q * Q);
+    copy_to_lds(lb + (size_t)spw * Q * Q, bi, ns * Q * Q);
+    copy_to_lds(lb + 2 * (size_t)spw * Q * Q, ob, ns * NDIR * Q * Q);
+    bd = lb;
+    bi = lb + (size_t)spw * Q * Q;
+    ob = lb + 2 * (size_t)spw * Q * Q;
   }
+  if (two)
+    copy_to_lds_transposed(lrows, A.agg_inv + (size_t)36 * a_lo * A.naggr, 6 * nwa, 6 * A.naggr);
+  __syncthreads();
   if (two) {   // P0's entries of the window, once per launch
     for (int e = t; e < win; e += COARSE_NT) {
       double dx, dy;
