@@ -791,14 +791,21 @@ __device__ __forceinline__ void blockinv_body(const Geo& g, const BlockArgs& A, 
   for (int v = 0; v < Q * Q; ++v) bi[v] = Bi[v];
 }
 
+// BLOCKINV_SETS sets per wave (the rest of its lanes idle): the per-set work
+// is one long dependent chain per lane, and its strided loads and stores of
+// whole 9 x 9 blocks touch one cache line per lane, so fewer sets per wave,
+// on more CUs, finish a little sooner.
+constexpr int BLOCKINV_SETS = 16;
 __global__ __launch_bounds__(64) void k_blockinv(Geo g, BlockArgs A) {
-  blockinv_body(g, A, blockIdx.x * 64 + threadIdx.x);
+  if (threadIdx.x >= BLOCKINV_SETS) return;
+  blockinv_body(g, A, blockIdx.x * BLOCKINV_SETS + threadIdx.x);
 }
 
 __global__ __launch_bounds__(64) void k_blockinv_batch(const BatchEntry* __restrict__ B,
                                                        const int* __restrict__ set_lat,
                                                        int nsets) {
-  const int gs = blockIdx.x * 64 + threadIdx.x;
+  if (threadIdx.x >= BLOCKINV_SETS) return;
+  const int gs = blockIdx.x * BLOCKINV_SETS + threadIdx.x;
   if (gs >= nsets) return;
   const BatchEntry& e = B[set_lat[gs]];
   blockinv_body(e.g, e.ba, gs - e.set0);
@@ -2060,7 +2067,8 @@ hipError_t launch_offdiag_batch(bool mixed, const BatchEntry* B, const int* set_
 hipError_t launch_blockinv_batch(const BatchEntry* B, const int* set_lat, int nsets,
                                  hipStream_t stream) {
   if (nsets <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_blockinv_batch, dim3((nsets + 63) / 64), dim3(64), 0, stream, B, set_lat, nsets);
+  hipLaunchKernelGGL(k_blockinv_batch, dim3((nsets + BLOCKINV_SETS - 1) / BLOCKINV_SETS), dim3(64), 0,
+                     stream, B, set_lat, nsets);
   return hipGetLastError();
 }
 
@@ -2113,7 +2121,7 @@ hipError_t launch_offdiag(bool mixed, const Geo& g, const float* ea, const uint8
 }
 
 hipError_t launch_blockinv(const Geo& g, const BlockArgs& a, hipStream_t stream) {
-  hipLaunchKernelGGL(k_blockinv, dim3((g.M + 63) / 64), dim3(64), 0, stream, g, a);
+  hipLaunchKernelGGL(k_blockinv, dim3((g.M + BLOCKINV_SETS - 1) / BLOCKINV_SETS), dim3(64), 0, stream, g, a);
   return hipGetLastError();
 }
 
