@@ -1105,6 +1105,7 @@ __device__ void agg_window_solve(const double* rows, int naggr, int nwa, int nr_
 // (K_a v) for one row of the workgroup's own sets, v from the LDS window that
 // starts at set w0.  bd / ob point at the own sets' diagonal and neighbour
 // blocks (an LDS copy or global memory), indexed from set s0.
+template <bool kWide>
 __device__ __forceinline__ double coarse_row(const Geo& g, const double* bd, const double* ob,
                                              int s, int s0, int m, const double* lv, int w0) {
   const int I = s % g.mx, J = s / g.mx;
@@ -1113,14 +1114,23 @@ __device__ __forceinline__ double coarse_row(const Geo& g, const double* bd, con
   double q = 0.0;
 #pragma unroll
   for (int l = 0; l < Q; ++l) q += b[l] * pv[l];
+  // kWide: branch-free over the six neighbours (an absent one reads the
+  // set's own window entries and contributes exact zeros), so that all 63
+  // block loads can be in flight at once when the blocks are in global
+  // memory.  It needs about 126 more registers; the batched kernel, held to
+  // 256, skips absent neighbours instead.
 #pragma unroll
   for (int dir = 0; dir < NDIR; ++dir) {
     const int I2 = I + nb_di(dir), J2 = J + nb_dj(dir);
-    if (I2 < 0 || I2 >= g.mx || J2 < 0 || J2 >= g.my) continue;
+    const bool ok = I2 >= 0 && I2 < g.mx && J2 >= 0 && J2 < g.my;
+    if (!kWide && !ok) continue;
     const double* o = ob + ((size_t)(s - s0) * NDIR + dir) * Q * Q + m * Q;
-    const double* pn = lv + (size_t)(J2 * g.mx + I2 - w0) * Q;
+    const double* pn = lv + (size_t)((ok ? J2 * g.mx + I2 : s) - w0) * Q;
 #pragma unroll
-    for (int l = 0; l < Q; ++l) q += o[l] * pn[l];
+    for (int l = 0; l < Q; ++l) {
+      const double ov = o[l];
+      q += (ok ? ov : 0.0) * pn[l];
+    }
   }
   return q;
 }
@@ -1221,6 +1231,7 @@ __device__ __forceinline__ void copy_to_lds_transposed(double* dst, const double
 // recurrences): per iteration one grid sum carries both dot products and
 // orders the publication of m = B^+ w, whose neighbour values the product
 // n = K_a m needs, so one grid synchronisation per iteration.
+template <bool kWide>
 __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, const int w,
                                             const int nwg) {
   extern __shared__ double lds[];
@@ -1329,7 +1340,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   }
   for (int e = t; e < nrow; e += COARSE_NT) {
     const int s = s0 + e / Q, m = e % Q;
-    const double y = warm ? coarse_row(g, bd, ob, s, s0, m, lw1, w0) : 0.0;
+    const double y = warm ? coarse_row<kWide>(g, bd, ob, s, s0, m, lw1, w0) : 0.0;
     const double aprev = lw1[(size_t)(s0 - w0) * Q + e];
     red6[4] += aprev * A.force[r0 + e];
     red6[5] += aprev * y;
@@ -1437,7 +1448,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
   }
   __syncthreads();
   for (int e = t; e < nrow; e += COARSE_NT) {
-    const double wv = coarse_row(g, bd, ob, s0 + e / Q, s0, e % Q, lw2, w0);
+    const double wv = coarse_row<kWide>(g, bd, ob, s0 + e / Q, s0, e % Q, lw2, w0);
     vw[e] = wv;
     vz[e] = 0.0;
     vq[e] = 0.0;
@@ -1588,9 +1599,9 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
     }
     if (!(alpha > 0.0)) break;
     if (two) coarse_space_correction(A, nwa, win, s_c, s_y, lw1, lrows, ldxy, lpart, 6 * alay.nwa_max);
-#pragma unroll 2
+#pragma unroll 1
     for (int e = t; e < nrow; e += COARSE_NT) {
-      const double n = coarse_row(g, bd, ob, s0 + e / Q, s0, e % Q, lw1, w0);
+      const double n = coarse_row<kWide>(g, bd, ob, s0 + e / Q, s0, e % Q, lw1, w0);
       const double m = lw1[(size_t)(s0 - w0) * Q + e];
       const double z = n + beta * vz[e];
       const double q = m + beta * vq[e];
@@ -1625,7 +1636,7 @@ __device__ __forceinline__ void coarse_body(const Geo& g, const CoarseArgs& A, c
 }
 
 __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
-  coarse_body(g, A, blockIdx.x, gridDim.x);
+  coarse_body<true>(g, A, blockIdx.x, gridDim.x);
 }
 
 // Fused launch: lattice b owns workgroups [wg0, wg0 + nwg) and runs its own
@@ -1634,7 +1645,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
 __global__ __launch_bounds__(COARSE_NT, 2) void k_coarse_batch(const BatchEntry* __restrict__ B,
                                                             const int* __restrict__ wg_lat) {
   const BatchEntry& e = B[wg_lat[blockIdx.x]];
-  coarse_body(e.g, e.ca, blockIdx.x - e.wg0, e.nwg);
+  coarse_body<false>(e.g, e.ca, blockIdx.x - e.wg0, e.nwg);
 }
 
 // ---------------------------------------------------------------------------
