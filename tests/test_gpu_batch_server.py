@@ -48,6 +48,37 @@ def test_batch_equals_alone_and_oracle(precision):
         assert max(info["rel_res_l1"], info["rel_res_l2"]) <= 1e-10
 
 
+@pytest.mark.parametrize("no_lds", [0, 1])
+def test_batch_equals_alone_upper_level_general_path(monkeypatch, no_lds):
+    """Several upper-level rows per thread with the blocks (and, with no_lds,
+    the PCG vectors) in global memory: the single-lattice kernel reads a row's
+    neighbour blocks branch-free, the batched one skips absent neighbours;
+    the two must still agree bit for bit."""
+    monkeypatch.setenv("TL_COARSE_SETS_PER_WG", "64")
+    monkeypatch.setenv("TL_COARSE_NO_LDS", str(no_lds))
+    shapes = [(200, 180, 16, "lognormal", 21), (150, 160, 16, "unit", 22)]
+    lats, fs, insts = [], [], []
+    for nx, ny, E, ea, seed in shapes:
+        inst = make_instance(nx, ny, seed=seed, ea=ea)
+        insts.append(inst)
+        lats.append(tl.tl_lattice_create(nx, ny, ea=inst.ea, fixed=inst.fixed, set_edge=E))
+        fs.append(torch.from_numpy(inst.f).cuda())
+    alone = []
+    for lat, f in zip(lats, fs):
+        u = torch.zeros_like(f)
+        info = tl.tl_solve(lat, f, u, precision=1, rtol=1e-10)
+        assert info["status"] == tl.TL_OK
+        alone.append(u.cpu().numpy())
+    us = [torch.zeros_like(f) for f in fs]
+    st, infos = tl.tl_solve_batch(lats, fs, us, precision=1, rtol=1e-10)
+    assert st == tl.TL_OK
+    for inst, u, ua in zip(insts, us, alone):
+        ub = u.cpu().numpy()
+        assert np.array_equal(ub, ua)
+        ref = solve(system_of(inst))
+        assert np.linalg.norm(ub.reshape(-1) - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
 def test_batch_with_repeated_lattice():
     insts, lats, fs = _setup()
     f2 = torch.from_numpy(make_instance(40, 33, seed=99, ea="lognormal").f).cuda()

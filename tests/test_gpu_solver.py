@@ -93,6 +93,24 @@ def test_solve_matches_oracle(nx, ny, E, ea, seed, precision):
     assert info["rel_res_l2"] == pytest.approx(R2o, rel=1e-3, abs=1e-13)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("sets_per_wg,no_lds", [(64, 0), (64, 1)])
+def test_upper_level_general_path_matches_oracle(monkeypatch, sets_per_wg, no_lds, precision):
+    """The upper level with several rows per thread and its blocks (and, with
+    no_lds, its PCG vectors) in global memory, the form large lattices take,
+    forced on a lattice the oracle solves in seconds."""
+    monkeypatch.setenv("TL_COARSE_SETS_PER_WG", str(sets_per_wg))
+    monkeypatch.setenv("TL_COARSE_NO_LDS", str(no_lds))
+    inst = make_instance(200, 180, seed=11, ea="lognormal")
+    S = system_of(inst)
+    us = solve(S)
+    u, info, _ = gpu_solve(inst, 16, precision, 1e-10)
+    assert info["status"] == tl.TL_OK
+    assert max(info["rel_res_l1"], info["rel_res_l2"]) <= 1e-10
+    err = np.linalg.norm(u.reshape(-1) - us) / np.linalg.norm(us)
+    assert err <= 1e-8, (err, info)
+
+
 def _oracle_blocks(Kc, sets, s):
     Q = om.Q
     I, J = s % sets.mx, s // sets.mx
