@@ -997,11 +997,6 @@ __device__ void grid_collect_window(const double* red, int slot, int nwg, double
   }
 }
 
-// The partial sums alone (no window).
-template <int NV>
-__device__ void grid_collect(const double* red, int slot, int nwg, double* sv) {
-  grid_collect_window<NV>(red, slot, nwg, sv, nullptr, nullptr, 0);
-}
 
 // Coarse space of the upper-level preconditioner.  Aggregates are runs of
 // agg_sets consecutive sets (whole workgroups); each carries six affine
