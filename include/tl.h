@@ -95,8 +95,10 @@ typedef struct {
     int32_t max_iters;         /* outer iterations; 0 = library default             */
     int32_t inner_iters;       /* relaxation PCG sweeps per set; 0 = default (16, or
                                   24 with 64 x 64 sets)                              */
-    int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default (100)   */
-    double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default 0.1 */
+    int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default: 100, or
+                                  200 for lattices of 16384 sets or more            */
+    double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default:
+                                  0.1, or 0.05 for lattices of 16384 sets or more   */
     int32_t warm_start;        /* 1: start from the free DOFs of u (else from 0)     */
     tl_trace* trace;           /* NULL, or diagnostics to fill                       */
     int32_t profile;           /* 1: time every kernel launch with HIP events on the
