@@ -98,7 +98,8 @@ typedef struct {
     int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default: 100, or
                                   200 for lattices of 16384 sets or more            */
     double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default:
-                                  0.1, or 0.05 for lattices of 16384 sets or more   */
+                                  0.05 for lattices of 16384 sets or more, else 0.15
+                                  for float64 with sets of at most 32 x 32, else 0.1 */
     int32_t warm_start;        /* 1: start from the free DOFs of u (else from 0)     */
     tl_trace* trace;           /* NULL, or diagnostics to fill                       */
     int32_t profile;           /* 1: time every kernel launch with HIP events on the

@@ -153,14 +153,21 @@ int default_inner_iters(int E) { return E >= 64 ? 24 : 16; }
 constexpr int kDefaultOverlap = 2;
 
 // The upper-level PCG's cap and relative tolerance when the caller leaves them
-// at 0.  From 16384 sets on (8192^2 and 16384^2 with 64 x 64 sets) a tighter
-// upper-level solve, 0.05 with a cap of 200, cuts the outer iterations enough
-// to pay for itself (16384^2: 434 -> 362 outer iterations, 16.4 -> 14.4 s;
-// 8192^2: 3.34 -> 3.24 s); below that 0.1 and 100 are as good or better
-// (1024^2 with 32 x 32 sets: 0.05 costs 9 %).
+// at 0, measured to 1e-8 (1e-10 at 16384^2):
+//  - from 16384 sets on (8192^2 and 16384^2 with 64 x 64 sets) a tighter
+//    upper-level solve, 0.05 with a cap of 200, cuts the outer iterations
+//    enough to pay for itself (16384^2: 434 -> 362 outer iterations, 16.4 ->
+//    14.4 s; 8192^2: 3.34 -> 3.24 s);
+//  - below that the float64 form with sets of at most 32 x 32 does better
+//    with a looser one, 0.15 (512^2 to 3000^2: 1-7 % faster), while with
+//    64 x 64 sets, and in the mixed form, 0.15 costs outer iterations
+//    (4096^2 float64 +4 %, 2048^2 mixed +27 %) and 0.1 stays.
 constexpr int kLargeUpperLevel = 16384;
 int default_coarse_iters(int M) { return M >= kLargeUpperLevel ? 200 : 100; }
-double default_coarse_rtol(int M) { return M >= kLargeUpperLevel ? 0.05 : 0.1; }
+double default_coarse_rtol(int M, int E, bool mixed) {
+  if (M >= kLargeUpperLevel) return 0.05;
+  return !mixed && E <= 32 ? 0.15 : 0.1;
+}
 
 tl_status resolve_opts(const tl_opts* o, Opts* r) {
   r->mixed = o && o->precision == TL_MIXED;
@@ -232,7 +239,7 @@ void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const doub
   ca->ctrl = w->ctrl;
   ca->max_iters = o.max_iters;
   ca->coarse_iters = o.coarse_iters > 0 ? o.coarse_iters : default_coarse_iters(L->g.M);
-  ca->coarse_rtol = o.coarse_rtol > 0.0 ? o.coarse_rtol : default_coarse_rtol(L->g.M);
+  ca->coarse_rtol = o.coarse_rtol > 0.0 ? o.coarse_rtol : default_coarse_rtol(L->g.M, L->g.E, o.mixed);
   ca->rtol = o.rtol;
   ca->warm = env_int("TL_COARSE_WARM", 1);
   ca->coarse_ref = env_int("TL_COARSE_REF", 0);
