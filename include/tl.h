@@ -103,7 +103,8 @@ typedef struct {
     int32_t warm_start;        /* 1: start from the free DOFs of u (else from 0)     */
     tl_trace* trace;           /* NULL, or diagnostics to fill                       */
     int32_t profile;           /* 1: time every kernel launch with HIP events on the
-                                  solve's stream (fills the *_ms fields of tl_info)  */
+                                  solve's stream (fills the *_ms fields of tl_info);
+                                  N > 1: only the launches of every N-th iteration  */
     int32_t overlap;           /* relax each set on its tile widened by this many
                                   nodes on every side, keeping the increment on the
                                   set (section 2.2 end): 1, 2 or 4; -1 = the set
@@ -122,7 +123,8 @@ typedef struct {
                                   (update/residual/relaxation) kernel launches     */
     double offdiag_ms;         /* ... of the boundary-block kernel launches         */
     double coarse_ms;          /* ... of the upper-level kernel launches            */
-    int32_t tile_launches;     /* launches those sums cover (iterations that ran)   */
+    int32_t tile_launches;     /* launches those sums cover (iterations that ran,
+                                  every N-th with profile = N)                      */
 } tl_info;
 
 /* Lattice geometry facts (for sizing buffers). */

@@ -335,7 +335,10 @@ tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, doub
       }
     }
     for (int c = 0; c < chunk && k <= o.max_iters; ++c, ++k) {
-      st_run = enqueue_iteration(L, w, o, f, st, o.profile ? &w->events[4 * c] : nullptr);
+      // profile = N > 1 times every N-th iteration (each event record adds a
+      // few microseconds between kernels)
+      const bool timed = o.profile && k % std::max(o.profile, 1) == 0;
+      st_run = enqueue_iteration(L, w, o, f, st, timed ? &w->events[4 * c] : nullptr);
       if (st_run != TL_OK) break;
     }
     if (st_run != TL_OK) break;
@@ -345,6 +348,7 @@ tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, doub
       // iterations after the one that stopped the solve are no-ops: not counted
       const int last = w->ctrl_host->done ? w->ctrl_host->iters : k - 1;
       for (int kk = k0; kk <= std::min(last, k - 1); ++kk) {
+        if (kk % std::max(o.profile, 1) != 0) continue;
         hipEvent_t* ev = &w->events[4 * (kk - k0)];
         float a = 0.f, b = 0.f, c = 0.f;
         TL_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));

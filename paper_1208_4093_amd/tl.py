@@ -216,7 +216,7 @@ def make_opts(precision=TL_FP64, rtol=1e-8, max_iters=0, inner_iters=0, coarse_i
     o.coarse_rtol = float(coarse_rtol)
     o.warm_start = 1 if warm_start else 0
     o.trace = C.pointer(trace) if trace is not None else C.POINTER(Trace)()
-    o.profile = 1 if profile else 0
+    o.profile = int(profile)
     o.overlap = int(overlap)
     return o
 
