@@ -288,7 +288,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   // 2. residual r = f - K u (float64) and the per-node relaxation operator.
   float kk[NPT][6];
   double2 r[NPT];
-  T ixx[NPT], ixy[NPT], iyy[NPT];    // inverse of the node's 2x2 diagonal block
+  T idet[NPT];                       // 1 / det of the node's 2x2 diagonal block
   bool act[NPT], own[NPT];
   double part[10];   // P1..P6, sum|r|, sum r^2, sum|f|, sum f^2
 #pragma unroll
@@ -332,7 +332,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     }
     const int n = t + k * NT, li = n % R, lj = n / R;
     r[k] = make_double2(0.0, 0.0);
-    ixx[k] = ixy[k] = iyy[k] = (T)0;
+    idet[k] = (T)0;
     if (!act[k]) continue;
     const int gi = ri0 + li, gj = rj0 + lj;
     const size_t p = pidx(g, gi, gj);
@@ -392,7 +392,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     const double kc = (double)kk[k][2] + kk[k][5];
     const double Dxx = ka + 0.25 * (kb + kc), Dyy = 0.75 * (kb + kc), Dxy = 0.5 * kS3 * (kb - kc);
     const double det = Dxx * Dyy - Dxy * Dxy;
-    ixx[k] = (T)(Dyy / det); ixy[k] = (T)(-Dxy / det); iyy[k] = (T)(Dxx / det);
+    idet[k] = (T)(1.0 / det);
   }
   // workgroup reduction of the 10 partials and the max |r|
   {
@@ -433,17 +433,25 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   //    Float32 form: r is scaled by 2^-e (e from max|r|) before rounding.
   const double rm = sfin[10];
   const double scl = (sizeof(T) == 4 && rm > 0.0 && isfinite(rm)) ? ldexp(1.0, -ilogb(rm)) : 1.0;
-  // Per node only x, r, p and K p stay in registers across the sweep's
-  // barriers; the diagonal block is rebuilt from the rod stiffnesses and
-  // z = B^-1 r is recomputed where it is needed (register pressure).
+  // Per node only x, r, p, K p and 1/det B stay in registers across the
+  // sweep's barriers (register pressure): the 2x2 diagonal block B is rebuilt
+  // from the rod stiffnesses, z = B^-1 r = adj(B) r / det B is formed once
+  // per sweep and waits for the direction update in the K p slot.
   T2 x[NPT], rr[NPT], pp[NPT], qq[NPT];
+  auto precond = [&](const int k, const T2 rv) {
+    const T ka = (T)kk[k][0] + (T)kk[k][3], kb = (T)kk[k][1] + (T)kk[k][4];
+    const T kc = (T)kk[k][2] + (T)kk[k][5];
+    const T Dxx = ka + (T)0.25 * (kb + kc), Dyy = (T)0.75 * (kb + kc);
+    const T Dxy = (T)(0.5 * kS3) * (kb - kc);
+    return mk2<T>(idet[k] * (Dyy * rv.x - Dxy * rv.y), idet[k] * (Dxx * rv.y - Dxy * rv.x));
+  };
   double rz_part = 0.0;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     x[k] = mk2<T>((T)0, (T)0);
     const double2 rk = kResidLds ? (act[k] ? sres[t + k * NT] : make_double2(0.0, 0.0)) : r[k];
     rr[k] = mk2<T>((T)(rk.x * scl), (T)(rk.y * scl));
-    pp[k] = mk2<T>(ixx[k] * rr[k].x + ixy[k] * rr[k].y, ixy[k] * rr[k].x + iyy[k] * rr[k].y);
+    pp[k] = precond(k, rr[k]);
     rz_part += (double)(rr[k].x * pp[k].x + rr[k].y * pp[k].y);
   }
   double rz = block_sum<NW>(rz_part, sred[0]);
@@ -485,17 +493,16 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     for (int k = 0; k < NPT; ++k) {
       x[k].x += alpha * pp[k].x;  x[k].y += alpha * pp[k].y;
       rr[k].x -= alpha * qq[k].x; rr[k].y -= alpha * qq[k].y;
-      const T zx = ixx[k] * rr[k].x + ixy[k] * rr[k].y, zy = ixy[k] * rr[k].x + iyy[k] * rr[k].y;
-      rzn_part += (double)(rr[k].x * zx + rr[k].y * zy);
+      qq[k] = precond(k, rr[k]);
+      rzn_part += (double)(rr[k].x * qq[k].x + rr[k].y * qq[k].y);
     }
     const double rzn = block_sum<NW>(rzn_part, sred[it & 1 ? 0 : 2]);
     const T beta = rz > 0.0 ? (T)(rzn / rz) : (T)0;
     rz = rzn;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      const T zx = ixx[k] * rr[k].x + ixy[k] * rr[k].y, zy = ixy[k] * rr[k].x + iyy[k] * rr[k].y;
-      pp[k].x = zx + beta * pp[k].x;
-      pp[k].y = zy + beta * pp[k].y;
+      pp[k].x = qq[k].x + beta * pp[k].x;
+      pp[k].y = qq[k].y + beta * pp[k].y;
     }
   }
 
