@@ -318,17 +318,19 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     }
   };
   // With 64 x 64 sets the loads of all of a thread's nodes do not fit in
-  // registers beside the arithmetic: each node's loads then precede its own
-  // arithmetic, fenced so the scheduler keeps that order.
+  // registers beside the arithmetic: the loads then run one node ahead of
+  // the arithmetic (node k + 1's issued before node k's arithmetic), fenced
+  // so the scheduler keeps that order.
   if constexpr (!kResidLds) {
 #pragma unroll
     for (int k = 0; k < NPT; ++k) load_node(k);
   }
+  if constexpr (kResidLds) load_node(0);
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     if constexpr (kResidLds) {
       __builtin_amdgcn_sched_barrier(0);
-      load_node(k);
+      if (k + 1 < NPT) load_node(k + 1);
     }
     const int n = t + k * NT, li = n % R, lj = n / R;
     r[k] = make_double2(0.0, 0.0);
@@ -579,20 +581,15 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     acc[KROW + 1] += xi * dr;
     acc[KROW + 2] += eta * dr;
   }
-  if constexpr (NPT <= 3) {
+  {
+    // 30 sums at once by halving exchanges: fewer lane moves than one
+    // reduction per value, at every set edge
     double a32[32];
 #pragma unroll
     for (int v = 0; v < 32; ++v) a32[v] = v < KROW + 3 ? acc[v] : 0.0;
     const double as = wave_sums<32>(a32);
     const int v = wave_sums_index<32>();
     if ((t & 1) == 0 && v < KROW + 3) sacc[t >> 6][v] = as;
-  } else {
-#pragma unroll
-    for (int v = 0; v < KROW + 3; ++v) acc[v] = wave_sum(acc[v]);
-    if ((t & 63) == 0) {
-#pragma unroll
-      for (int v = 0; v < KROW + 3; ++v) sacc[t >> 6][v] = acc[v];
-    }
   }
   __syncthreads();
   if (t < KROW + 3) {
