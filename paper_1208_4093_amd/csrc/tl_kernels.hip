@@ -601,11 +601,12 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
 }
 
 // Waves per SIMD the register allocation must allow.  The float tile of a
-// 32 x 32 set with 512 threads is held to 128 registers, so that two tiles
-// share a CU and one's barriers overlap the other's work: it spills a little
-// but runs 1.2-1.3x faster.  The double tile spills far more at that bound
-// and runs slower, so it keeps one tile per CU, as do regions widened by
-// more than 2 nodes (four nodes per thread).
+// 32 x 32 set with 512 threads and an overlap up to 2 (a tuning choice) is
+// held to 128 registers, so that two tiles share a CU and one's barriers overlap the
+// other's work: it spills a little but runs 1.2-1.3x faster.  (With 256
+// threads two tiles share a CU at 256 registers without this bound.)  The
+// double tile spills inside its sweep loop at that bound and runs slower, so
+// it keeps one tile per CU, as do regions widened by more than 2 nodes.
 template <typename T, int E, int NT, int OV>
 constexpr int tile_waves_per_eu() { return sizeof(T) == 4 && E == 32 && NT == 512 && OV <= 2 ? 4 : 1; }
 
@@ -2003,13 +2004,19 @@ int grid_for(size_t n, int nt, int cap) {
 // Threads per tile workgroup for each set edge, precision and overlap
 // (measured without overlap: 256 for E = 32; 512 for E = 64 in float32, 1024
 // in float64, where 512 threads spill).  With overlap the region holds
-// (E + 2 OV)^2 nodes: 256 threads for E = 16, 512 for 32, 1024 for 64.
+// (E + 2 OV)^2 nodes: 256 threads for E = 16, 1024 for 64; for 32, 512 in
+// float64 (three nodes per thread; 256 or 1024 threads were 1.3x slower) and
+// 256 in float32 for overlaps up to 2 (five or six nodes per thread in at
+// most 256 registers, two tiles per CU, no spills: 1.02-1.07x faster than
+// 512 threads from 1024^2 up, 1.05x slower when there are no more sets than
+// CUs).  The choice depends on the lattice's set edge, form and overlap only,
+// so a lattice gets the same kernel alone and in a fused batch.
 // TL_TILE_THREADS overrides for tuning.
 static int tile_threads(int E, bool mixed, int ov) {
   const char* v = getenv("TL_TILE_THREADS");
   const int env = v && *v ? atoi(v) : 0;
   if (E == 16) return 256;
-  if (ov > 0) return E == 32 ? (env == 256 || env == 512 ? env : 512) : 1024;
+  if (ov > 0) return E == 32 ? (env == 256 || env == 512 ? env : (mixed && ov <= 2 ? 256 : 512)) : 1024;
   if (E == 32) return env == 256 || env == 512 || env == 1024 ? env : 256;
   return env == 512 || env == 1024 ? env : (mixed ? 512 : 1024);
 }
