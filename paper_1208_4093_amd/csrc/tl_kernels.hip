@@ -601,12 +601,12 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
 }
 
 // Waves per SIMD the register allocation must allow.  The float tile of a
-// 32 x 32 set with 512 threads and an overlap up to 2 (a tuning choice) is
-// held to 128 registers, so that two tiles share a CU and one's barriers overlap the
-// other's work: it spills a little but runs 1.2-1.3x faster.  (With 256
-// threads two tiles share a CU at 256 registers without this bound.)  The
-// double tile spills inside its sweep loop at that bound and runs slower, so
-// it keeps one tile per CU, as do regions widened by more than 2 nodes.
+// 32 x 32 set with 512 threads and an overlap up to 2 is held to 128
+// registers, so that two tiles share a CU and one's barriers overlap the
+// other's work: it spills a little (not in the sweep loop) but runs 1.2-1.3x
+// faster.  The double tile spills inside its sweep loop at that bound and
+// runs slower, so it keeps one tile per CU, as do regions widened by more
+// than 2 nodes.
 template <typename T, int E, int NT, int OV>
 constexpr int tile_waves_per_eu() { return sizeof(T) == 4 && E == 32 && NT == 512 && OV <= 2 ? 4 : 1; }
 
@@ -2004,19 +2004,23 @@ int grid_for(size_t n, int nt, int cap) {
 // Threads per tile workgroup for each set edge, precision and overlap
 // (measured without overlap: 256 for E = 32; 512 for E = 64 in float32, 1024
 // in float64, where 512 threads spill).  With overlap the region holds
-// (E + 2 OV)^2 nodes: 256 threads for E = 16, 1024 for 64; for 32, 512 in
-// float64 (three nodes per thread; 256 or 1024 threads were 1.3x slower) and
-// 256 in float32 for overlaps up to 2 (five or six nodes per thread in at
-// most 256 registers, two tiles per CU, no spills: 1.02-1.07x faster than
-// 512 threads from 1024^2 up, 1.05x slower when there are no more sets than
-// CUs).  The choice depends on the lattice's set edge, form and overlap only,
-// so a lattice gets the same kernel alone and in a fused batch.
-// TL_TILE_THREADS overrides for tuning.
+// (E + 2 OV)^2 nodes: 256 threads for E = 16; for 64, 512 in float32 with
+// overlaps up to 2 (ten nodes per thread in 256 registers; 1.02x faster than
+// 1024 threads at 128) and 1024 otherwise; for 32, 512 (three nodes per
+// thread; in float64 256 or 1024 threads were 1.3x slower; in float32 256
+// threads, two tiles per CU without spills, were 1.02-1.07x faster on single
+// lattices from 1024^2 up but 1.02x slower in fused batches and served
+// streams of small lattices).  The choice depends on the lattice's set edge,
+// form and overlap only, so a lattice gets the same kernel alone and in a
+// fused batch.  TL_TILE_THREADS overrides for tuning.
 static int tile_threads(int E, bool mixed, int ov) {
   const char* v = getenv("TL_TILE_THREADS");
   const int env = v && *v ? atoi(v) : 0;
   if (E == 16) return 256;
-  if (ov > 0) return E == 32 ? (env == 256 || env == 512 ? env : (mixed && ov <= 2 ? 256 : 512)) : 1024;
+  if (ov > 0) {
+    if (E == 32) return env == 256 || env == 512 ? env : 512;
+    return env == 512 || env == 1024 ? env : (mixed && ov <= 2 ? 512 : 1024);
+  }
   if (E == 32) return env == 256 || env == 512 || env == 1024 ? env : 256;
   return env == 512 || env == 1024 ? env : (mixed ? 512 : 1024);
 }
@@ -2029,7 +2033,7 @@ bool tile_overlap_supported(int ov) { return ov == 0 || ov == 1 || ov == 2 || ov
   else if (E == 32 && nt == 256) X(T, 32, 256, OV);                \
   else if (E == 32 && nt == 512) X(T, 32, 512, OV);                \
   else if (E == 32 && OV == 0) X(T, 32, 1024, 0);                  \
-  else if (E == 64 && nt == 512 && OV == 0) X(T, 64, 512, 0);      \
+  else if (E == 64 && nt == 512) X(T, 64, 512, OV);                \
   else if (E == 64) X(T, 64, 1024, OV);                            \
   else return hipErrorInvalidValue;
 #define TL_TILE_OVERLAPS(X, T)                 \
