@@ -318,19 +318,24 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     }
   };
   // With 64 x 64 sets the loads of all of a thread's nodes do not fit in
-  // registers beside the arithmetic: the loads then run one node ahead of
-  // the arithmetic (node k + 1's issued before node k's arithmetic), fenced
-  // so the scheduler keeps that order.
+  // registers beside the arithmetic: the loads then run kAhead nodes ahead of
+  // the arithmetic (node k + kAhead's issued before node k's arithmetic),
+  // fenced so the scheduler keeps that order: two with 256 registers per
+  // thread (at most 512 threads), one with 128.
   if constexpr (!kResidLds) {
 #pragma unroll
     for (int k = 0; k < NPT; ++k) load_node(k);
   }
-  if constexpr (kResidLds) load_node(0);
+  constexpr int kAhead = NT <= 512 ? 2 : 1;
+  if constexpr (kResidLds) {
+#pragma unroll
+    for (int k = 0; k < kAhead && k < NPT; ++k) load_node(k);
+  }
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     if constexpr (kResidLds) {
       __builtin_amdgcn_sched_barrier(0);
-      if (k + 1 < NPT) load_node(k + 1);
+      if (k + kAhead < NPT) load_node(k + kAhead);
     }
     const int n = t + k * NT, li = n % R, lj = n / R;
     r[k] = make_double2(0.0, 0.0);
@@ -398,9 +403,10 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   }
   // workgroup reduction of the 10 partials and the max |r|
   {
-    // (the many-value wave sums pay off below 64 x 64 sets; at 64 x 64 the
-    //  registers they hold spill)
-    if constexpr (NPT <= 3) {
+    // (the many-value wave sums pay off where their registers fit: up to
+    //  three nodes per thread, or 256 registers per thread with at most 512
+    //  threads; with 64 x 64 sets in 1024 threads they spill)
+    if constexpr (NPT <= 3 || NT <= 512) {
       double p16[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) p16[v] = v < 10 ? part[v] : 0.0;
