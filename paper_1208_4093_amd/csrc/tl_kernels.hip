@@ -551,21 +551,31 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     double xi, eta;
     set_coords(ri0 + li, rj0 + lj, i0, j0, tw, th, inv_hs, xi, eta);
     const double dax = (double)x[k].x, day = (double)x[k].y;
-    const double ka = (double)kk[k][0] + kk[k][3];
-    const double kb = (double)kk[k][1] + kk[k][4];
-    const double kc = (double)kk[k][2] + kk[k][5];
-    const double Dxx = ka + 0.25 * (kb + kc), Dyy = 0.75 * (kb + kc), Dxy = 0.5 * kS3 * (kb - kc);
-    const double Ddx = Dxx * dax + Dxy * day, Ddy = Dxy * dax + Dyy * day;
-    double w7x = Ddx, w7y = Ddy, w8x = xi * Ddx, w8y = xi * Ddy, w9x = eta * Ddx, w9y = eta * Ddy;
+    // k^Inner applied rod by rod, each rod's diagonal part beside its
+    // coupling to the neighbour.  In the float32 form the stiffnesses pass an
+    // empty asm first: otherwise the compiler reuses the float64 conversions
+    // of the residual step and keeps them live across the whole relaxation
+    // (whose own arithmetic is float32), which with many nodes per thread
+    // spills them.  (The float64 form converts them in its relaxation too.)
+    float kf[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      kf[b] = kk[k][b];
+      if constexpr (sizeof(T) == 4) asm volatile("" : "+v"(kf[b]));
+    }
+    double w7x = 0.0, w7y = 0.0, w8x = 0.0, w8y = 0.0, w9x = 0.0, w9y = 0.0;
 #pragma unroll
     for (int b = 0; b < 6; ++b) {
       const T2 db = sp[c + off[b]];
-      const double s7 = (double)kk[k][kidx[b]] * (nvx[b] * (double)db.x + nvy[b] * (double)db.y);
-      const double s8 = s7 * (xi + dxi[b]);
-      const double s9 = s7 * (eta + deta[b]);
-      w7x -= s7 * nvx[b]; w7y -= s7 * nvy[b];
-      w8x -= s8 * nvx[b]; w8y -= s8 * nvy[b];
-      w9x -= s9 * nvx[b]; w9y -= s9 * nvy[b];
+      const double kr = (double)kf[kidx[b]];
+      const double sa = kr * (nvx[b] * dax + nvy[b] * day);
+      const double s7 = kr * (nvx[b] * (double)db.x + nvy[b] * (double)db.y);
+      const double d7 = sa - s7;
+      const double d8 = xi * sa - (xi + dxi[b]) * s7;
+      const double d9 = eta * sa - (eta + deta[b]) * s7;
+      w7x += d7 * nvx[b]; w7y += d7 * nvy[b];
+      w8x += d8 * nvx[b]; w8y += d8 * nvy[b];
+      w9x += d9 * nvx[b]; w9y += d9 * nvy[b];
     }
     const double wx[3] = {w7x, w8x, w9x}, wy[3] = {w7y, w8y, w9y};
 #pragma unroll
