@@ -58,11 +58,11 @@ WORKLOADS = {
     # calibrated on copy kernels); None when the kernel has changed since the
     # counters were taken.
     "c2": dict(n=1024, E=32, ea="unit", rtol=1e-8, headline="fp64",
-               traffic_bytes=(33032.3 * 2.0 + 33088.0) * 1024,
+               traffic_bytes=(63524.1 * 2.0 + 84345.6) * 1024,
                desc="triangle lattice 1024x1024 nodes (2,097,152 DOF), EA=1, L=1, left edge "
                     "clamped, loads N(0,1) seed 0, sets 32x32 nodes, stop at rel. residual 1e-8"),
     "c3": dict(n=16384, E=64, ea="lognormal", rtol=1e-10, headline="mixed",
-               traffic_bytes=(7577616.1 * 2.0 + 6315482.9) * 1024,
+               traffic_bytes=(7575589.2 * 2.0 + 6315514.2) * 1024,
                desc="triangle lattice 16384x16384 nodes (536,870,912 DOF), EA lognormal(0,0.5), "
                     "left edge clamped, loads N(0,1) seed 0, sets 64x64 nodes, mixed precision, "
                     "stop at rel. residual 1e-10"),

@@ -478,19 +478,28 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       const int n = t + k * NT;
       const int c = (n / R + 1) * W + (n % R + 1);
       const T2 pa = pp[k];
-      const T ka = (T)kk[k][0] + (T)kk[k][3], kb = (T)kk[k][1] + (T)kk[k][4];
-      const T kc = (T)kk[k][2] + (T)kk[k][5];
+      // (float64 form: the stiffnesses pass an empty asm so that each sweep
+      //  converts them afresh instead of the compiler holding the residual
+      //  step's conversions in registers across the relaxation)
+      float kq[6];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        kq[b] = kk[k][b];
+        if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(kq[b]));
+      }
+      const T ka = (T)kq[0] + (T)kq[3], kb = (T)kq[1] + (T)kq[4];
+      const T kc = (T)kq[2] + (T)kq[5];
       const T Dxx = ka + (T)0.25 * (kb + kc), Dyy = (T)0.75 * (kb + kc);
       const T Dxy = (T)(0.5 * kS3) * (kb - kc);
       T qx = Dxx * pa.x + Dxy * pa.y;
       T qy = Dxy * pa.x + Dyy * pa.y;
       T2 pb; T s;
-      pb = sp[c + 1];     s = (T)kk[k][0] * pb.x;                                qx -= s;
-      pb = sp[c - 1];     s = (T)kk[k][3] * pb.x;                                qx -= s;
-      pb = sp[c + W];     s = (T)kk[k][1] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
-      pb = sp[c - W];     s = (T)kk[k][4] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
-      pb = sp[c + W - 1]; s = (T)kk[k][2] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
-      pb = sp[c - W + 1]; s = (T)kk[k][5] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+      pb = sp[c + 1];     s = (T)kq[0] * pb.x;                                qx -= s;
+      pb = sp[c - 1];     s = (T)kq[3] * pb.x;                                qx -= s;
+      pb = sp[c + W];     s = (T)kq[1] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
+      pb = sp[c - W];     s = (T)kq[4] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
+      pb = sp[c + W - 1]; s = (T)kq[2] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+      pb = sp[c - W + 1]; s = (T)kq[5] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
       qq[k] = mk2<T>(qx, qy);
       pq_part += (double)(pa.x * qx + pa.y * qy);
     }
@@ -552,16 +561,15 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     set_coords(ri0 + li, rj0 + lj, i0, j0, tw, th, inv_hs, xi, eta);
     const double dax = (double)x[k].x, day = (double)x[k].y;
     // k^Inner applied rod by rod, each rod's diagonal part beside its
-    // coupling to the neighbour.  In the float32 form the stiffnesses pass an
-    // empty asm first: otherwise the compiler reuses the float64 conversions
-    // of the residual step and keeps them live across the whole relaxation
-    // (whose own arithmetic is float32), which with many nodes per thread
-    // spills them.  (The float64 form converts them in its relaxation too.)
+    // coupling to the neighbour.  The stiffnesses pass an empty asm first:
+    // otherwise the compiler reuses the float64 conversions of the residual
+    // step and keeps them live across the whole relaxation, which with many
+    // nodes per thread spills them.
     float kf[6];
 #pragma unroll
     for (int b = 0; b < 6; ++b) {
       kf[b] = kk[k][b];
-      if constexpr (sizeof(T) == 4) asm volatile("" : "+v"(kf[b]));
+      asm volatile("" : "+v"(kf[b]));
     }
     double w7x = 0.0, w7y = 0.0, w8x = 0.0, w8y = 0.0, w9x = 0.0, w9y = 0.0;
 #pragma unroll
@@ -616,15 +624,14 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   }
 }
 
-// Waves per SIMD the register allocation must allow.  The float tile of a
-// 32 x 32 set with 512 threads and an overlap up to 2 is held to 128
-// registers, so that two tiles share a CU and one's barriers overlap the
-// other's work: it spills a little (not in the sweep loop) but runs 1.2-1.3x
-// faster.  The double tile spills inside its sweep loop at that bound and
-// runs slower, so it keeps one tile per CU, as do regions widened by more
-// than 2 nodes.
+// Waves per SIMD the register allocation must allow.  The tile of a 32 x 32
+// set with 512 threads and an overlap up to 2 is held to 128 registers, so
+// that two tiles share a CU and one's barriers overlap the other's work: it
+// spills a little (not in the sweep loop) but runs faster, 1.2-1.3x in
+// float32 and 1.1-1.2x in float64.  Regions widened by more than 2 nodes
+// keep one tile per CU.
 template <typename T, int E, int NT, int OV>
-constexpr int tile_waves_per_eu() { return sizeof(T) == 4 && E == 32 && NT == 512 && OV <= 2 ? 4 : 1; }
+constexpr int tile_waves_per_eu() { return E == 32 && NT == 512 && OV <= 2 ? 4 : 1; }
 
 template <typename T, int E, int NT, int OV>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(tile_waves_per_eu<T, E, NT, OV>())))
