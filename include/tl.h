@@ -93,8 +93,9 @@ typedef struct {
     tl_precision precision;
     double rtol;               /* stop when max(R1, R2) <= rtol (Eq. 19, both norms) */
     int32_t max_iters;         /* outer iterations; 0 = library default             */
-    int32_t inner_iters;       /* relaxation PCG sweeps per set; 0 = default (16, or
-                                  24 with 64 x 64 sets)                              */
+    int32_t inner_iters;       /* relaxation PCG sweeps per set; 0 = default: 24
+                                  with 64 x 64 sets, 20 for float64 with 32 x 32
+                                  sets, else 16                                     */
     int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default: 100, or
                                   200 for lattices of 16384 sets or more            */
     double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default:

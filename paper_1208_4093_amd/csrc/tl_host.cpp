@@ -141,8 +141,11 @@ CoarseShape coarse_shape(const Geo& g) {
 // with the two-level upper level (1024^2 and 2048^2 with 32 x 32 sets,
 // 4096^2 with 64 x 64): solve time falls from 10 sweeps up to about 16 for
 // 32 x 32 sets (1024^2 float64 70 -> 65 ms) and about 24 for 64 x 64
-// (4096^2 mixed 1148 -> 911 ms), then rises again.
-int default_inner_iters(int E) { return E >= 64 ? 24 : 16; }
+// (4096^2 mixed 1148 -> 911 ms), then rises again.  Since the float64 tile
+// of a 32 x 32 set runs two to a CU its sweeps are cheaper and 20 is best
+// in that form (1024^2 42.5 -> 40.5 ms, 2048^2 lognormal 117.8 -> 112.9 ms;
+// 24 is slower again); the float32 form stays fastest at 16.
+int default_inner_iters(int E, bool mixed) { return E >= 64 ? 24 : (E == 32 && !mixed ? 20 : 16); }
 
 // Defaults when the caller leaves a field at 0.  Measured on 1024^2 (unit EA,
 // 32 x 32 sets), 2048^2 and 4096^2 (lognormal EA, 32 and 64 sets) to 1e-8:
@@ -199,7 +202,7 @@ void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const doub
   ta->force = w->force;
   ta->nrm = w->nrm;
   ta->ctrl = w->ctrl;
-  ta->inner_iters = o.inner > 0 ? o.inner : default_inner_iters(L->g.E);
+  ta->inner_iters = o.inner > 0 ? o.inner : default_inner_iters(L->g.E, o.mixed);
   ta->rhs_mode = L->ufix != nullptr;
   oa->d0 = w->d[0];
   oa->d1 = w->d[1];
