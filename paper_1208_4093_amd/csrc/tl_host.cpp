@@ -143,8 +143,9 @@ CoarseShape coarse_shape(const Geo& g) {
 // 32 x 32 sets (1024^2 float64 70 -> 65 ms) and about 24 for 64 x 64
 // (4096^2 mixed 1148 -> 911 ms), then rises again.  Since the float64 tile
 // of a 32 x 32 set runs two to a CU its sweeps are cheaper and 20 is best
-// in that form (1024^2 42.5 -> 40.5 ms, 2048^2 lognormal 117.8 -> 112.9 ms;
-// 24 is slower again); the float32 form stays fastest at 16.
+// in that form (1024^2 42.5 -> 40.5 ms, 2048^2 lognormal 117.8 -> 112.9 ms,
+// 512^2 26.0 -> 23.5 ms; 18, 22 and 24 are slower); the float32 form stays
+// fastest at 16.
 int default_inner_iters(int E, bool mixed) { return E >= 64 ? 24 : (E == 32 && !mixed ? 20 : 16); }
 
 // Defaults when the caller leaves a field at 0.  Measured on 1024^2 (unit EA,
