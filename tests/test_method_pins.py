@@ -187,3 +187,124 @@ def test_planted_region_off_by_one_is_caught(monkeypatch):
     monkeypatch.setattr(om, "relaxation_region", lambda sets, I, w: real(sets, I, max(w - 1, 0)))
     with pytest.raises(AssertionError):
         test_overlap_increment_equals_dense_region_solve(2)
+
+
+# ----------------------------------------------- the modes themselves (Eq. 9-14)
+# The iterates depend only on the span of each set's modes (the representative
+# node and the gradient scale are free, Eq. 10 and 14), so the modes are pinned
+# by their spans, computed from node positions written out here:
+#   modes 1-6 span the affine fields b + A x on the set's free nodes (Eq. 9-10);
+#   mode 7 is the relaxation increment itself (Eq. 13);
+#   modes 7-9 span {d, x d, y d} for the increment d (Eq. 13-14);
+# and every mode vanishes outside its set and on clamped nodes.
+
+def _positions(nx, ny):
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    return (i + 0.5 * j).reshape(-1), (j * np.sqrt(3.0) / 2.0).reshape(-1)
+
+
+def _set_columns(U, Q, I):
+    return U[:, Q * I:Q * I + Q].toarray()
+
+
+def _in_span(B, v):
+    """Relative distance of v from the column span of B."""
+    c, *_ = np.linalg.lstsq(B, v, rcond=None)
+    return np.linalg.norm(B @ c - v) / max(np.linalg.norm(v), 1e-300)
+
+
+def _mode_case():
+    nx, ny, E = 37, 29, 16                    # ragged sets, a clamped left edge
+    inst = make_instance(nx, ny, seed=31, ea="lognormal")
+    S = system_of(inst)
+    sets = om.make_sets(nx, ny, E)
+    delta = np.random.default_rng(32).standard_normal(2 * nx * ny) * S.free
+    return nx, ny, S, sets, delta
+
+
+def test_modes_span_affine_fields_and_relaxation_products():
+    nx, ny, S, sets, delta = _mode_case()
+    Q = om.Q
+    U = om.mode_matrix(S, sets, delta)
+    x, y = _positions(nx, ny)
+    rng = np.random.default_rng(33)
+    node_set = np.repeat(sets.of_node, 2)
+    for I in range(sets.M):
+        rows = np.flatnonzero((node_set == I) & S.free)
+        B = _set_columns(U, Q, I)
+        # support: the set's free DOFs only
+        outside = np.ones(U.shape[0], bool)
+        outside[rows] = False
+        assert np.all(B[outside] == 0.0)
+        nodes = rows[0::2] // 2
+        if nodes.size < 3:
+            continue
+        G = B[rows, :6]
+        assert np.linalg.matrix_rank(G, tol=1e-10 * np.abs(G).max()) == 6
+        for _ in range(3):
+            A, b = rng.standard_normal((2, 2)), rng.standard_normal(2)
+            field = np.empty(rows.size)
+            field[0::2] = b[0] + A[0, 0] * x[nodes] + A[0, 1] * y[nodes]
+            field[1::2] = b[1] + A[1, 0] * x[nodes] + A[1, 1] * y[nodes]
+            assert _in_span(G, field) <= 1e-12
+        d = delta[rows]
+        assert np.array_equal(B[rows, 6], d)
+        xd, yd = np.repeat(x[nodes], 2) * d, np.repeat(y[nodes], 2) * d
+        R = B[rows, 6:9]
+        assert np.linalg.matrix_rank(R, tol=1e-10 * np.abs(R).max()) == 3
+        for v in (d, xd, yd):
+            assert _in_span(R, v) <= 1e-12
+
+
+def test_planted_duplicate_gradient_mode_is_caught(monkeypatch):
+    """Mode 4, (y - y_I, 0), replaced by a copy of mode 3, (x - x_I, 0)."""
+    real = om.mode_matrix
+
+    def dup(S, sets, delta):
+        U = real(S, sets, delta).tolil()
+        U[:, 3::om.Q] = U[:, 2::om.Q]
+        return U.tocsr()
+    monkeypatch.setattr(om, "mode_matrix", dup)
+    with pytest.raises(AssertionError):
+        test_modes_span_affine_fields_and_relaxation_products()
+
+
+def test_planted_transposed_gradient_mode_is_caught(monkeypatch):
+    """Mode 6, (0, y - y_I), built as (0, x - x_I): a copy of mode 5."""
+    real = om.mode_matrix
+
+    def tr(S, sets, delta):
+        U = real(S, sets, delta).tolil()
+        U[:, 5::om.Q] = U[:, 4::om.Q]
+        return U.tocsr()
+    monkeypatch.setattr(om, "mode_matrix", tr)
+    with pytest.raises(AssertionError):
+        test_modes_span_affine_fields_and_relaxation_products()
+
+
+def test_planted_wrong_weight_in_relaxation_mode_is_caught(monkeypatch):
+    """Mode 9 weighted by x (a copy of mode 8) instead of y (Eq. 14)."""
+    real = om.mode_matrix
+
+    def wrong(S, sets, delta):
+        U = real(S, sets, delta).tolil()
+        U[:, 8::om.Q] = U[:, 7::om.Q]
+        return U.tocsr()
+    monkeypatch.setattr(om, "mode_matrix", wrong)
+    with pytest.raises(AssertionError):
+        test_modes_span_affine_fields_and_relaxation_products()
+
+
+def test_planted_mode_on_clamped_node_is_caught(monkeypatch):
+    """Translation mode left non-zero on the clamped nodes of a set."""
+    real = om.mode_matrix
+
+    def leaky(S, sets, delta):
+        U = real(S, sets, delta).tolil()
+        clamped = np.flatnonzero(~S.free)
+        for d in clamped[0::2]:
+            U[d, om.Q * sets.of_node[d // 2]] = 1.0
+        return U.tocsr()
+    monkeypatch.setattr(om, "mode_matrix", leaky)
+    with pytest.raises(AssertionError):
+        test_modes_span_affine_fields_and_relaxation_products()

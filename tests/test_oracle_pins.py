@@ -234,3 +234,84 @@ def test_planted_wrong_sign_in_offdiagonal_is_caught(monkeypatch):
     monkeypatch.setattr(osolve, "assemble", flipped)
     with pytest.raises(AssertionError):
         test_2x2_compliance_matches_hand_derivation()
+
+
+# ------------------------------------------------ Eq. 19 at a non-zero iterate
+
+def _golden_residual_cases():
+    cases = {}
+    for line in (GOLDEN / "lattice_2x2_residual.txt").read_text().splitlines():
+        if not line.strip() or line.startswith("#"):
+            continue
+        t = line.split()
+        R1 = float(Fraction(t[1])) + float(Fraction(t[2])) * math.sqrt(3)
+        R2 = math.sqrt(float(Fraction(t[3])))
+        en = None if t[4] == "-" else float(Fraction(t[4]))
+        cases[int(t[0])] = (R1, R2, en)
+    return cases
+
+
+def _case_2x2(case):
+    """The two hand-derived states of tests/golden/lattice_2x2_residual.txt."""
+    inst = make_instance(2, 2, seed=0)
+    inst.f[:] = 0.0
+    inst.f[0, 1] = (2.0, 1.0)                 # load on node A = (i=1, j=0)
+    if case == 2:
+        inst.u_fixed[0, 0] = (0.5, 0.0)       # clamped node O = (0, 0) prescribed
+    S = system_of(inst)
+    u = S.u_c.copy()
+    u[2 * 1] = 1.0                            # u_A = (1, 0)
+    return S, u
+
+
+@pytest.mark.parametrize("case", [1, 2])
+def test_relative_residuals_at_nonzero_iterate_match_hand_values(case):
+    import oracle.solve as osolve
+    R1, R2, en = _golden_residual_cases()[case]
+    S, u = _case_2x2(case)
+    got1, got2 = osolve.rel_residuals(S, u)
+    assert got1 == pytest.approx(R1, rel=1e-14)
+    assert got2 == pytest.approx(R2, rel=1e-14)
+    if en is not None:
+        assert osolve.energy(S, u) == pytest.approx(en, rel=1e-14)
+
+
+def _plant(monkeypatch, fn):
+    import oracle.solve as osolve
+    monkeypatch.setattr(osolve, "rel_residuals", fn)
+
+
+def test_planted_squared_r2_is_caught(monkeypatch):
+    import oracle.solve as osolve
+    real = osolve.rel_residuals
+    _plant(monkeypatch, lambda S, u: (real(S, u)[0], real(S, u)[1] ** 2))
+    with pytest.raises(AssertionError):
+        test_relative_residuals_at_nonzero_iterate_match_hand_values(1)
+
+
+def test_planted_max_norm_r1_is_caught(monkeypatch):
+    import oracle.solve as osolve
+    real = osolve.rel_residuals
+
+    def max_norm(S, u):
+        r = osolve.residual(S, u)[S.free]
+        return float(np.abs(r).max() / np.abs(S.rhs).max()), real(S, u)[1]
+    _plant(monkeypatch, max_norm)
+    with pytest.raises(AssertionError):
+        test_relative_residuals_at_nonzero_iterate_match_hand_values(1)
+
+
+def test_planted_unconstrained_normaliser_is_caught(monkeypatch):
+    """Dividing by the load f_f instead of the constrained right-hand side
+    f_f - K_fc u_c (the two differ only with prescribed displacements)."""
+    import oracle.solve as osolve
+    real = osolve.rel_residuals
+
+    def by_load(S, u):
+        r = osolve.residual(S, u)[S.free]
+        f = S.f[S.free]
+        return (float(np.abs(r).sum() / np.abs(f).sum()),
+                float(np.sqrt((r * r).sum() / (f * f).sum())))
+    _plant(monkeypatch, by_load)
+    with pytest.raises(AssertionError):
+        test_relative_residuals_at_nonzero_iterate_match_hand_values(2)
