@@ -31,6 +31,14 @@
  *   host threads are serialised internally.  Device pointers are hipMalloc'd
  *   (or PyTorch) memory on the current device.
  *
+ * Concurrency across streams
+ *   The upper-level kernel is a persistent grid whose workgroups must all be
+ *   resident at once.  Calls from several host threads (tl_solve on different
+ *   lattices or streams, tl_solve_batch, the server's worker) are admitted
+ *   process-wide: their persistent grids run together only while all of
+ *   their workgroups fit the device's CUs together, else one after another,
+ *   one chunk of outer iterations at a time.  Results do not depend on this.
+ *
  * Errors
  *   Every call returns a tl_status; nothing aborts or throws across the ABI.
  *   TL_E_NOCONV still writes the last iterate to u and fills the tl_info.
@@ -125,7 +133,12 @@ typedef struct {
     double offdiag_ms;         /* ... of the boundary-block kernel launches         */
     double coarse_ms;          /* ... of the upper-level kernel launches            */
     int32_t tile_launches;     /* launches those sums cover (iterations that ran,
-                                  every N-th with profile = N)                      */
+                                  every N-th with profile = N).  tl_solve_batch
+                                  with opts->profile: tile_ms and tile_launches
+                                  cover the fused tile launches of the lattice's
+                                  set edge while at least one lattice of that
+                                  edge was still iterating; offdiag_ms and
+                                  coarse_ms cover the whole call                   */
 } tl_info;
 
 /* Lattice geometry facts (for sizing buffers). */
@@ -140,7 +153,12 @@ typedef struct {
  * constant part of the upper-level diagonal blocks (translation and
  * gradient modes, Eq. 6 with Eq. 9-10).  Returns TL_E_INVAL without touching
  * the device when nx or ny < 2, fewer than two nodes are clamped, set_edge is
- * not 0/16/32/64, or an EA is negative or not finite (host-side input only). */
+ * not 0/16/32/64, or an EA is negative or not finite (host-side input only);
+ * and TL_E_INVAL after the copy when the same holds for device input, or when
+ * a free node's own 2 x 2 stiffness block is singular (no rod, or only
+ * collinear rods, hold it), since K is then not positive definite (Eq. 1
+ * assumes it is).  Larger mechanisms are not detected here; a solve of such a
+ * lattice ends with TL_E_NONFINITE or TL_E_NOCONV. */
 tl_status tl_lattice_create(const tl_lattice_desc* desc, void* hip_stream, tl_lattice** out);
 void tl_lattice_destroy(tl_lattice* lat);
 tl_status tl_lattice_get_facts(const tl_lattice* lat, tl_lattice_facts* out);
@@ -161,8 +179,12 @@ tl_status tl_solve(tl_lattice* lat, const double* f_dev, double* u_dev,
  * the device; groups run one after another.  Each lattice's result is bit for
  * bit the one tl_solve gives it alone (its kernels, set edge and reduction
  * orders depend on that lattice only).  infos[k] receives lattice k's result
- * (ms = device time of the whole call); the return value is TL_OK when every
- * lattice converged, else the first failing status. */
+ * (ms = wall time from the call's start until lattice k's finish was seen at
+ * the end of a chunk of iterations: its latency within the batch); the return
+ * value is TL_OK when every lattice converged, else the first failing status.
+ * With opts->profile the chunks are not captured: every launch is timed with
+ * HIP events (see tl_info) and the control blocks are read after every outer
+ * iteration, so such a call is slower than an unprofiled one. */
 tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const* f_dev,
                          double* const* u_dev, const tl_opts* opts, tl_info* infos,
                          void* hip_stream);
@@ -180,10 +202,14 @@ tl_status tl_residual(tl_lattice* lat, const double* f_dev, const double* u_dev,
  * admitted requests of a precision together in fused launches, eight outer
  * iterations at a time, retires each as it converges and admits waiting
  * requests at once.  Results are bit for bit those of tl_solve alone.
- * tl_submit returns TL_E_BUDGET for a request that could never be admitted. */
+ * tl_submit returns TL_E_BUDGET for a request that could never be admitted.
+ * It records an event on hip_stream (NULL = the null stream): the request's
+ * kernels wait for the work enqueued there before the call, so f_dev may be
+ * produced by a kernel that has not finished yet.  u_dev is complete when
+ * tl_poll reports the request finished. */
 tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, tl_server** out);
 tl_status tl_submit(tl_server* srv, tl_lattice* lat, const double* f_dev, double* u_dev,
-                    const tl_opts* opts, uint64_t* ticket);
+                    const tl_opts* opts, void* hip_stream, uint64_t* ticket);
 /* TL_PENDING until the request has finished; then its final status, with
  * out filled (out->ms = submit-to-finish wall time). */
 tl_status tl_poll(tl_server* srv, uint64_t ticket, tl_info* out);
@@ -191,6 +217,7 @@ tl_status tl_poll(tl_server* srv, uint64_t ticket, tl_info* out);
 void tl_server_destroy(tl_server* srv);
 
 const char* tl_strerror(tl_status s);
+
 
 #ifdef __cplusplus
 }

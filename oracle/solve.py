@@ -181,6 +181,6 @@ def solve(sys_: System, rtol: float = 1e-13) -> np.ndarray:
     if n <= 6000:
         return solve_dense(sys_)
     bw = _bandwidth(sys_.Kff)
-    if n * (bw + 1) * 8 <= 3 << 30 and n * bw * bw <= 4e11:
+    if n * (bw + 1) * 8 <= 6 << 30 and n * bw * bw <= 1e12:
         return solve_banded(sys_)
     return solve_pcg(sys_, rtol=rtol)

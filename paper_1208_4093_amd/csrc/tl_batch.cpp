@@ -59,8 +59,18 @@ struct Job {
   tl_info info{};
   uint64_t ticket = 0;
   Clock::time_point t_submit, t_done;
+  Clock::time_point t_seen;  // when the host first saw the solve stopped
+  bool seen = false;
   bool finished = false;
   bool lock_lattice = true;  // false when the caller already holds the lattice lock
+  hipEvent_t ready = nullptr;  // tl_submit: recorded on the caller's stream
+
+  Job() = default;
+  Job(const Job&) = delete;
+  Job& operator=(const Job&) = delete;
+  ~Job() {
+    if (ready) (void)hipEventDestroy(ready);
+  }
 };
 
 // Workgroup plan of a fused upper-level launch.  Each lattice gets the
@@ -224,14 +234,22 @@ struct FusedBatch {
     return TL_OK;
   }
 
-  // One outer iteration of every lattice in the batch.
-  tl_status enqueue_iteration(hipStream_t st) const {
-    for (int k = 0; k < kGroups; ++k)
+  // One outer iteration of every lattice in the batch.  ev (optional, kEvents
+  // entries): recorded before the first launch, after each tile group, after
+  // the boundary-block and block-inverse launches and after the upper level.
+  static constexpr int kEvents = kGroups + 3;
+  tl_status enqueue_iteration(hipStream_t st, hipEvent_t* ev = nullptr) const {
+    if (ev) TB_TRY(hipEventRecord(ev[0], st));
+    for (int k = 0; k < kGroups; ++k) {
       TB_TRY(launch_tile_batch(mixed, kEdges[k / 4], kOverlaps[k % 4], d_entries, d_tile_lat[k],
                                ntiles[k], st));
+      if (ev) TB_TRY(hipEventRecord(ev[1 + k], st));
+    }
     TB_TRY(launch_offdiag_batch(mixed, d_entries, d_set_lat, nsets, st));
     TB_TRY(launch_blockinv_batch(d_entries, d_set_lat, nsets, st));
+    if (ev) TB_TRY(hipEventRecord(ev[kGroups + 1], st));
     TB_TRY(launch_coarse_batch(d_entries, d_wg_lat, nwg, lds, st));
+    if (ev) TB_TRY(hipEventRecord(ev[kGroups + 2], st));
     return TL_OK;
   }
 
@@ -296,12 +314,23 @@ void drop_work(Job* j) {
   j->w = nullptr;
 }
 
+// Kernel times of a profiled tl_solve_batch call.
+struct BatchProfile {
+  double tile_ms[3] = {0.0, 0.0, 0.0};   // by set edge 16, 32, 64
+  int tile_launches[3] = {0, 0, 0};
+  double offdiag_ms = 0.0, coarse_ms = 0.0;
+};
+
+int edge_slot(int E) { return E == 16 ? 0 : E == 32 ? 1 : 2; }
+
 // Run one co-resident group of a tl_solve_batch call to completion: start
 // every solve, build the fused tables, capture one chunk of iterations in a
 // hipGraph and replay it until every lattice of the group has stopped, then
-// copy out and certify each result (marking its job finished).
+// copy out and certify each result (marking its job finished).  With a
+// profile, iterations are enqueued one at a time with timing events and the
+// control blocks read after each.
 tl_status run_group(std::vector<Job*>& group, const std::map<tl_lattice*, int>& seen,
-                    const Opts& o, hipStream_t st) {
+                    const Opts& o, hipStream_t st, BatchProfile* prof) {
   tl_status first = TL_OK;
   FusedBatch fb;
   for (Job* j : group) {
@@ -316,11 +345,17 @@ tl_status run_group(std::vector<Job*>& group, const std::map<tl_lattice*, int>& 
     fb.jobs.push_back(j);
   }
   if (first == TL_OK) first = fb.build(st);
+  std::vector<hipEvent_t> ev;
+  if (first == TL_OK && prof) {
+    ev.resize(FusedBatch::kEvents, nullptr);
+    for (hipEvent_t& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) { first = TL_E_DEVICE; break; }
+  }
   if (first == TL_OK) {
-    const int chunk = 8;
+    const int chunk = prof ? 1 : 8;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    bool use_graph = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    bool use_graph = !prof && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (use_graph) {
       tl_status s = TL_OK;
       for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb.enqueue_iteration(st);
@@ -332,17 +367,50 @@ tl_status run_group(std::vector<Job*>& group, const std::map<tl_lattice*, int>& 
     int rounds = 0;
     const int max_rounds = o.max_iters / chunk + 2;
     const int n = (int)group.size();
+    std::vector<char> live(n, 1);
     for (;;) {
       tl_status s = TL_OK;
-      if (use_graph) {
-        s = hipGraphLaunch(exec, st) == hipSuccess ? TL_OK : TL_E_DEVICE;
-      } else {
-        for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb.enqueue_iteration(st);
+      {
+        PersistentGuard guard(fb.nwg, st);
+        if (use_graph) {
+          s = hipGraphLaunch(exec, st) == hipSuccess ? TL_OK : TL_E_DEVICE;
+        } else {
+          for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb.enqueue_iteration(st, prof ? ev.data() : nullptr);
+        }
+        if (s == TL_OK) s = fb.read_ctrl(st);
       }
-      if (s == TL_OK) s = fb.read_ctrl(st);
       if (s != TL_OK) { first = s; break; }
+      if (prof) {
+        // the iteration just run: its tile groups with a lattice still iterating
+        bool edge_live[3] = {false, false, false};
+        for (int b = 0; b < n; ++b)
+          if (live[b]) edge_live[edge_slot(group[b]->L->g.E)] = true;
+        float ms[FusedBatch::kEvents] = {};
+        for (int k = 1; k < FusedBatch::kEvents && s == TL_OK; ++k)
+          if (hipEventElapsedTime(&ms[k], ev[k - 1], ev[k]) != hipSuccess) s = TL_E_DEVICE;
+        if (s != TL_OK) { first = s; break; }
+        bool launched[3] = {false, false, false};
+        for (int k = 0; k < FusedBatch::kGroups; ++k) {
+          const int slot = k / 4;
+          if (!edge_live[slot] || fb.ntiles[k] == 0) continue;
+          prof->tile_ms[slot] += ms[1 + k];
+          launched[slot] = true;
+        }
+        for (int e = 0; e < 3; ++e) prof->tile_launches[e] += launched[e];
+        prof->offdiag_ms += ms[FusedBatch::kGroups + 1];
+        prof->coarse_ms += ms[FusedBatch::kGroups + 2];
+      }
+      const auto now = Clock::now();
       bool all = true;
-      for (int b = 0; b < n; ++b) all = all && (fb.h_ctrl[b].done || fb.h_ctrl[b].err);
+      for (int b = 0; b < n; ++b) {
+        const bool stopped = fb.h_ctrl[b].done || fb.h_ctrl[b].err;
+        if (stopped && !group[b]->seen) {
+          group[b]->seen = true;
+          group[b]->t_seen = now;
+        }
+        live[b] = !stopped;
+        all = all && stopped;
+      }
       if (all) break;
       if (++rounds > max_rounds) { first = TL_E_DEVICE; break; }
     }
@@ -355,6 +423,8 @@ tl_status run_group(std::vector<Job*>& group, const std::map<tl_lattice*, int>& 
       }
     }
   }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
   fb.release();
   return first;
 }
@@ -417,7 +487,10 @@ void server_loop(tl_server* S) {
       }
     }
     for (Job* j : admitted) {
-      tl_status s = alloc_and_start(j, S->stream);
+      // the request's load may still be in production on the caller's stream
+      tl_status s = j->ready && hipStreamWaitEvent(S->stream, j->ready, 0) != hipSuccess
+                        ? TL_E_DEVICE : TL_OK;
+      if (s == TL_OK) s = alloc_and_start(j, S->stream);
       if (s != TL_OK) {
         drop_work(j);
         std::lock_guard<std::mutex> lock(S->mu);
@@ -440,8 +513,11 @@ void server_loop(tl_server* S) {
         s = fb[m].build(S->stream);
         dirty[m] = false;
       }
-      for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb[m].enqueue_iteration(S->stream);
-      if (s == TL_OK) s = fb[m].read_ctrl(S->stream);
+      if (s == TL_OK) {
+        PersistentGuard guard(fb[m].nwg, S->stream);
+        for (int c = 0; c < chunk && s == TL_OK; ++c) s = fb[m].enqueue_iteration(S->stream);
+        if (s == TL_OK) s = fb[m].read_ctrl(S->stream);
+      }
       std::vector<Job*> still;
       for (size_t b = 0; b < live[m].size(); ++b) {
         Job* j = live[m][b];
@@ -483,8 +559,11 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
   Opts o;
   if (resolve_opts(opts, &o) != TL_OK) return TL_E_INVAL;
   o.trace = nullptr;
+  BatchProfile prof;
+  BatchProfile* pp = o.profile ? &prof : nullptr;
   o.profile = 0;
   hipStream_t user = (hipStream_t)hip_stream;
+  const auto t_call = Clock::now();
   std::vector<Job> jobs(n);
   std::map<tl_lattice*, int> seen;
   for (int i = 0; i < n; ++i) seen[lats[i]]++;
@@ -524,17 +603,23 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
       ++next;
     }
     if (group.empty()) { first = TL_E_BUDGET; break; }   // one lattice that never fits
-    first = run_group(group, seen, o, st);
+    first = run_group(group, seen, o, st, pp);
   }
   (void)hipEventRecord(e1, st);
   (void)hipEventSynchronize(e1);
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
+  const auto t_end = Clock::now();
   for (int i = 0; i < n; ++i) {
     Job& j = jobs[i];
     if (!j.finished) j.status = first != TL_OK ? first : TL_E_DEVICE;
     j.info.status = j.status;
-    j.info.ms = ms;
+    j.info.ms = std::chrono::duration<double, std::milli>((j.seen ? j.t_seen : t_end) - t_call).count();
+    if (pp) {
+      const int e = edge_slot(j.L->g.E);
+      j.info.tile_ms = prof.tile_ms[e];
+      j.info.tile_launches = prof.tile_launches[e];
+      j.info.offdiag_ms = prof.offdiag_ms;
+      j.info.coarse_ms = prof.coarse_ms;
+    }
     infos[i] = j.info;
     if (j.status != TL_OK && first == TL_OK) first = j.status;
     drop_work(&j);
@@ -565,7 +650,7 @@ tl_status tl_server_create(size_t hbm_budget_bytes, int32_t max_slots, tl_server
 }
 
 tl_status tl_submit(tl_server* S, tl_lattice* L, const double* f_dev, double* u_dev,
-                    const tl_opts* opts, uint64_t* ticket) {
+                    const tl_opts* opts, void* hip_stream, uint64_t* ticket) {
   if (!S || !L || !f_dev || !u_dev || !ticket) return TL_E_INVAL;
   Job* j = new (std::nothrow) Job();
   if (!j) return TL_E_NOMEM;
@@ -576,6 +661,14 @@ tl_status tl_submit(tl_server* S, tl_lattice* L, const double* f_dev, double* u_
   j->o.trace = nullptr;
   j->o.profile = 0;
   if (job_bytes(j) > S->budget || !coresident({j})) { delete j; return TL_E_BUDGET; }
+  // order the request after the caller's work on its stream (the load may be
+  // produced there); the worker's stream waits on this event
+  if (hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess) {
+    j->ready = nullptr;
+    delete j;
+    return TL_E_DEVICE;
+  }
+  if (hipEventRecord(j->ready, (hipStream_t)hip_stream) != hipSuccess) { delete j; return TL_E_DEVICE; }
   j->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lock(S->mu);

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -314,81 +315,105 @@ tl_status certify(const tl_lattice* L, const double* f, const double* u, double*
 }
 
 tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, double* u,
-                    tl_info* info, hipStream_t st) {
-  hipEvent_t e0, e1;
-  TL_TRY(hipEventCreate(&e0));
-  TL_TRY(hipEventCreate(&e1));
-  TL_TRY(launch_init_state(L->g, L->mask, L->ufix, (const double2*)u, o.warm, w->u[0], w->u[1],
-                           w->d[0], w->d[1], o.mixed, w->a, w->flags, w->ctrl, st));
+                    tl_info* info, hipStream_t st, Ctrl* ctrl_host, bool use_events) {
+  using Clock = std::chrono::steady_clock;
+  const auto t_start = Clock::now();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto drop_events = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    e0 = e1 = nullptr;
+  };
+  if (use_events) {
+    TL_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { drop_events(); return TL_E_DEVICE; }
+  }
+  hipError_t he = launch_init_state(L->g, L->mask, L->ufix, (const double2*)u, o.warm, w->u[0],
+                                    w->u[1], w->d[0], w->d[1], o.mixed, w->a, w->flags, w->ctrl, st);
+  if (he != hipSuccess) { drop_events(); return from_hip(he); }
   {
     const tl_status cs = ensure_coarse_space(L, w, o, f, st);
-    if (cs != TL_OK) return cs;
+    if (cs != TL_OK) { drop_events(); return cs; }
   }
-  TL_TRY(hipEventRecord(e0, st));
+  if (e0 && (he = hipEventRecord(e0, st)) != hipSuccess) { drop_events(); return from_hip(he); }
+  const int nwg = coarse_shape(L->g).nwg;
   int k = 0, chunk = 4;
   tl_status st_run = TL_OK;
   double t_tile = 0.0, t_off = 0.0, t_coarse = 0.0;
   int n_timed = 0;
+  const bool profile = use_events && o.profile;
   for (;;) {
     const int k0 = k;
-    if (o.profile) {
+    if (profile) {
       while ((int)w->events.size() < 4 * chunk) {
         hipEvent_t e;
-        TL_TRY(hipEventCreate(&e));
+        if (hipEventCreate(&e) != hipSuccess) { st_run = TL_E_DEVICE; break; }
         w->events.push_back(e);
       }
-    }
-    for (int c = 0; c < chunk && k <= o.max_iters; ++c, ++k) {
-      // profile = N > 1 times every N-th iteration (each event record adds a
-      // few microseconds between kernels)
-      const bool timed = o.profile && k % std::max(o.profile, 1) == 0;
-      st_run = enqueue_iteration(L, w, o, f, st, timed ? &w->events[4 * c] : nullptr);
       if (st_run != TL_OK) break;
     }
+    {
+      // the chunk's persistent upper-level grids are admitted process-wide
+      // and the guard waits for the chunk before it is released
+      PersistentGuard guard(nwg, st);
+      for (int c = 0; c < chunk && k <= o.max_iters; ++c, ++k) {
+        // profile = N > 1 times every N-th iteration (each event record adds a
+        // few microseconds between kernels)
+        const bool timed = profile && k % std::max(o.profile, 1) == 0;
+        st_run = enqueue_iteration(L, w, o, f, st, timed ? &w->events[4 * c] : nullptr);
+        if (st_run != TL_OK) break;
+      }
+      if (st_run == TL_OK &&
+          hipMemcpyAsync(ctrl_host, w->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st) != hipSuccess)
+        st_run = TL_E_DEVICE;
+      if (st_run == TL_OK && hipStreamSynchronize(st) != hipSuccess) st_run = TL_E_DEVICE;
+    }
     if (st_run != TL_OK) break;
-    TL_TRY(hipMemcpyAsync(w->ctrl_host, w->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    TL_TRY(hipStreamSynchronize(st));
-    if (o.profile) {
+    if (profile) {
       // iterations after the one that stopped the solve are no-ops: not counted
-      const int last = w->ctrl_host->done ? w->ctrl_host->iters : k - 1;
+      const int last = ctrl_host->done ? ctrl_host->iters : k - 1;
       for (int kk = k0; kk <= std::min(last, k - 1); ++kk) {
         if (kk % std::max(o.profile, 1) != 0) continue;
         hipEvent_t* ev = &w->events[4 * (kk - k0)];
         float a = 0.f, b = 0.f, c = 0.f;
-        TL_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));
-        TL_TRY(hipEventElapsedTime(&b, ev[1], ev[2]));
-        TL_TRY(hipEventElapsedTime(&c, ev[2], ev[3]));
+        if (hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[1], ev[2]) != hipSuccess ||
+            hipEventElapsedTime(&c, ev[2], ev[3]) != hipSuccess) {
+          st_run = TL_E_DEVICE;
+          break;
+        }
         t_tile += a;
         t_off += b;
         t_coarse += c;
         ++n_timed;
       }
+      if (st_run != TL_OK) break;
     }
-    if (w->ctrl_host->err) { st_run = TL_E_DEVICE; break; }
-    if (w->ctrl_host->done) break;
+    if (ctrl_host->err) { st_run = TL_E_DEVICE; break; }
+    if (ctrl_host->done) break;
     if (k > o.max_iters) { st_run = TL_E_DEVICE; break; }
     chunk = std::min(chunk * 2, 64);
   }
-  TL_TRY(hipEventRecord(e1, st));
   if (st_run != TL_OK) {
     (void)hipStreamSynchronize(st);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    drop_events();
     return st_run;
   }
-  const Ctrl c = *w->ctrl_host;
+  const Ctrl c = *ctrl_host;
   const int kf = c.iters;
-  TL_TRY(launch_copy_out(L->g, w->u[(kf + 1) & 1], (double2*)u, st));
-  if (o.trace && o.trace->delta && kf >= 1)
-    TL_TRY(launch_copy_delta(o.mixed, L->g, w->d[kf & 1], (double2*)o.trace->delta, st));
-  TL_TRY(hipEventSynchronize(e1));
+  if (e1 && (he = hipEventRecord(e1, st)) != hipSuccess) { drop_events(); return from_hip(he); }
+  he = launch_copy_out(L->g, w->u[(kf + 1) & 1], (double2*)u, st);
+  if (he == hipSuccess && o.trace && o.trace->delta && kf >= 1)
+    he = launch_copy_delta(o.mixed, L->g, w->d[kf & 1], (double2*)o.trace->delta, st);
   float ms = 0.f;
-  TL_TRY(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (he == hipSuccess && e1) he = hipEventSynchronize(e1);
+  if (he == hipSuccess && e1) he = hipEventElapsedTime(&ms, e0, e1);
+  drop_events();
+  if (he != hipSuccess) return from_hip(he);
   double out3[3];
   tl_status cs = certify(L, f, u, nullptr, out3, st);
   if (cs != TL_OK) return cs;
+  if (!use_events) ms = (float)std::chrono::duration<double, std::milli>(Clock::now() - t_start).count();
   if (info) {
     info->status = (tl_status)c.status;
     info->iters = kf;
@@ -404,6 +429,54 @@ tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, doub
   }
   if (c.status == 0 && !(std::isfinite(out3[0]) && std::isfinite(out3[1]))) return TL_E_NONFINITE;
   return (tl_status)c.status;
+}
+
+// ---------------------------------------------------------------------------
+// Admission of persistent upper-level grids (see PersistentGuard).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kXcds = 8;          // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kMaxDevices = 64;
+
+struct DeviceGate {
+  std::mutex mu;
+  std::condition_variable cv;
+  int cap = 0;                    // CUs per XCD
+  int used = 0;                   // CUs per XCD claimed by the grids in flight
+  int in_flight = 0;
+};
+DeviceGate g_gates[kMaxDevices];
+
+}  // namespace
+
+PersistentGuard::PersistentGuard(int nwg, hipStream_t stream) : stream_(stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+  DeviceGate& G = g_gates[dev];
+  std::unique_lock<std::mutex> lock(G.mu);
+  if (G.cap == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+    G.cap = std::max(1, cus / kXcds);
+  }
+  const int demand = (std::max(nwg, 1) + kXcds - 1) / kXcds;
+  G.cv.wait(lock, [&] { return G.in_flight == 0 || G.used + demand <= G.cap; });
+  G.used += demand;
+  ++G.in_flight;
+  dev_ = dev;
+  demand_ = demand;
+}
+
+PersistentGuard::~PersistentGuard() {
+  (void)hipStreamSynchronize(stream_);
+  DeviceGate& G = g_gates[dev_];
+  {
+    std::lock_guard<std::mutex> lock(G.mu);
+    G.used -= demand_;
+    --G.in_flight;
+  }
+  G.cv.notify_all();
 }
 
 Work* lattice_work(tl_lattice* L, bool mixed, int hist_cap, tl_status* err) {
@@ -470,6 +543,25 @@ tl_status tl_lattice_create(const tl_lattice_desc* desc, void* hip_stream, tl_la
       nfix = (size_t)ny;
     }
     if (nfix < 2) return TL_E_INVAL;
+    // every free node's own 2 x 2 block (its rods' k n n^T) must be regular
+    auto rod = [&](int d, int i, int j) -> double {
+      if (i < 0 || i >= nx || j < 0 || j >= ny) return 0.0;
+      const bool gone = d == 0 ? i == nx - 1 : d == 1 ? j == ny - 1 : (i == 0 || j == ny - 1);
+      if (gone) return 0.0;
+      return desc->ea ? (double)desc->ea[(size_t)d * nn + (size_t)j * nx + i] : 1.0;
+    };
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const bool fx = desc->fixed ? desc->fixed[(size_t)j * nx + i] != 0 : i == 0;
+        if (fx) continue;
+        const double ka = rod(0, i, j) + rod(0, i - 1, j);
+        const double kb = rod(1, i, j) + rod(1, i, j - 1);
+        const double kc = rod(2, i, j) + rod(2, i + 1, j - 1);
+        const double dxx = ka + 0.25 * (kb + kc), dyy = 0.75 * (kb + kc);
+        const double dxy = 0.43301270189221932338 * (kb - kc);
+        const double tr = dxx + dyy, det = dxx * dyy - dxy * dxy;
+        if (!(tr > 0.0) || !(det > 1e-12 * tr * tr)) return TL_E_INVAL;
+      }
     if (desc->u_fixed)
       for (size_t n = 0; n < 2 * nn; ++n)
         if (!std::isfinite(desc->u_fixed[n])) return TL_E_NONFINITE;
@@ -500,7 +592,7 @@ tl_status tl_lattice_create(const tl_lattice_desc* desc, void* hip_stream, tl_la
   if ((e = dalloc(&p, (size_t)L->g.M * 36 * sizeof(double))) != hipSuccess) return fail(from_hip(e));
   L->g1 = (double*)p;
   int* stats;
-  if ((e = dalloc(&p, 2 * sizeof(int))) != hipSuccess) return fail(from_hip(e));
+  if ((e = dalloc(&p, 3 * sizeof(int))) != hipSuccess) return fail(from_hip(e));
   stats = (int*)p;
   if ((e = dalloc(&p, residual_partials(L->g) * sizeof(double))) != hipSuccess) return fail(from_hip(e));
   L->res_part = (double*)p;
@@ -534,13 +626,13 @@ tl_status tl_lattice_create(const tl_lattice_desc* desc, void* hip_stream, tl_la
   }
   e = launch_pad_copy_stats(L->g, ea_src, fx_src, ea_src == nullptr, fx_src == nullptr, L->ea,
                             L->mask, stats, st);
-  int hs[2] = {0, 0};
+  int hs[3] = {0, 0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (tmp_ea) (void)hipFree(tmp_ea);
   if (tmp_fx) (void)hipFree(tmp_fx);
   if (e != hipSuccess) return fail(from_hip(e));
-  if (hs[0] != 0 || hs[1] < 2) return fail(TL_E_INVAL);
+  if (hs[0] != 0 || hs[1] < 2 || hs[2] != 0) return fail(TL_E_INVAL);
   if (desc->u_fixed) {
     if ((e = dalloc(&p, nn * sizeof(double2))) != hipSuccess) return fail(from_hip(e));
     L->ufix = (double2*)p;
@@ -627,7 +719,7 @@ tl_status tl_solve(tl_lattice* L, const double* f_dev, double* u_dev, const tl_o
   tl_status err = TL_OK;
   Work* w = lattice_work(L, o.mixed, o.max_iters + 1, &err);
   if (!w) return err;
-  return run_solve(L, w, o, f_dev, u_dev, info, (hipStream_t)hip_stream);
+  return run_solve(L, w, o, f_dev, u_dev, info, (hipStream_t)hip_stream, w->ctrl_host, true);
 }
 
 tl_status tl_residual(tl_lattice* L, const double* f_dev, const double* u_dev, double* r_dev,

@@ -227,7 +227,8 @@ hipError_t launch_residual(const Geo& g, const float* ea, const uint8_t* mask,
                            double* partials, double* out5, hipStream_t stream);
 size_t residual_partials(const Geo& g);
 // Pad and copy the lattice description; stats[0] += non-finite or negative
-// EA count, stats[1] += clamped node count.
+// EA count, stats[1] += clamped node count, stats[2] += free nodes whose own
+// 2 x 2 stiffness block is singular.
 hipError_t launch_pad_copy_stats(const Geo& g, const float* ea_user, const uint8_t* fixed_user,
                                  int ea_default, int fixed_default, float* ea, uint8_t* mask,
                                  int* stats, hipStream_t stream);

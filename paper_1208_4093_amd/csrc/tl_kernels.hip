@@ -1871,6 +1871,23 @@ __global__ void k_pad_copy(Geo g, const float* __restrict__ ea_user,
     const uint8_t fx = fixed_default ? (uint8_t)(i == 0) : (uint8_t)(fixed_user[n] != 0);
     mask[p] = fx;
     if (fx) atomicAdd(&stats[1], 1);
+    if (!fx) {
+      // the free node's own 2 x 2 block, sum of k n n^T over its (up to six)
+      // rods; singular when no rod, or only collinear rods, hold the node
+      auto rod = [&](int d, int ii, int jj) -> double {
+        if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny) return 0.0;
+        const bool gone = d == 0 ? ii == g.nx - 1 : d == 1 ? jj == g.ny - 1 : (ii == 0 || jj == g.ny - 1);
+        if (gone) return 0.0;
+        const double v = ea_default ? 1.0 : (double)ea_user[(size_t)d * nn + (size_t)jj * g.nx + ii];
+        return v >= 0.0 && v <= 3.4e38 ? v : 0.0;
+      };
+      const double ka = rod(0, i, j) + rod(0, i - 1, j);
+      const double kb = rod(1, i, j) + rod(1, i, j - 1);
+      const double kc = rod(2, i, j) + rod(2, i + 1, j - 1);
+      const double dxx = ka + 0.25 * (kb + kc), dyy = 0.75 * (kb + kc), dxy = 0.5 * kS3 * (kb - kc);
+      const double tr = dxx + dyy, det = dxx * dyy - dxy * dxy;
+      if (!(tr > 0.0) || !(det > 1e-12 * tr * tr)) atomicAdd(&stats[2], 1);
+    }
   }
 }
 

@@ -96,9 +96,35 @@ tl_status enqueue_iteration(const tl_lattice* L, Work* w, const Opts& o, const d
                             hipStream_t st, hipEvent_t* ev = nullptr);
 // The lattice's cached work space for one precision (caller holds L->mu).
 Work* lattice_work(tl_lattice* L, bool mixed, int hist_cap, tl_status* err);
+// One solve on a prepared work space.  ctrl_host receives the control block
+// between chunks (pinned memory, or any host memory); with use_events = false
+// no HIP event is created (no kernel timing; info->ms is host wall time).
 tl_status run_solve(tl_lattice* L, Work* w, const Opts& o, const double* f, double* u,
-                    tl_info* info, hipStream_t st);
+                    tl_info* info, hipStream_t st, Ctrl* ctrl_host, bool use_events);
 tl_status certify(const tl_lattice* L, const double* f, const double* u, double* r,
                   double out3[3], hipStream_t st);
+
+// Process-wide admission of persistent upper-level grids on the current
+// device.  Every workgroup of such a grid must be resident at once (its grid
+// sums wait on all of them), so two grids enqueued on different streams by
+// different calls must not each be left partly resident.  Workgroups are
+// dispatched round-robin over the XCDs, so a grid of n workgroups places at
+// most ceil(n / XCDs) on any one; counting each as a whole CU, grids run
+// together only while those counts fit an XCD's CUs, and a grid that needs
+// more (a fused batch at two workgroups per CU) runs alone.  The guard is
+// held from the enqueue of a chunk of iterations until the host has seen
+// that chunk finish: its destructor synchronises `stream` before releasing.
+class PersistentGuard {
+ public:
+  PersistentGuard(int nwg, hipStream_t stream);
+  ~PersistentGuard();
+  PersistentGuard(const PersistentGuard&) = delete;
+  PersistentGuard& operator=(const PersistentGuard&) = delete;
+
+ private:
+  int dev_ = -1;
+  int demand_ = 0;
+  hipStream_t stream_ = nullptr;
+};
 
 }  // namespace tl

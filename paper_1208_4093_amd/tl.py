@@ -87,7 +87,7 @@ def load():
         lib.tl_residual.restype = C.c_int
         lib.tl_server_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(P)]
         lib.tl_server_create.restype = C.c_int
-        lib.tl_submit.argtypes = [P, P, P, P, C.POINTER(Opts), C.POINTER(C.c_uint64)]
+        lib.tl_submit.argtypes = [P, P, P, P, C.POINTER(Opts), P, C.POINTER(C.c_uint64)]
         lib.tl_submit.restype = C.c_int
         lib.tl_poll.argtypes = [P, C.c_uint64, C.POINTER(Info)]
         lib.tl_poll.restype = C.c_int
@@ -298,12 +298,15 @@ def tl_server_create(hbm_budget_bytes: int, max_slots: int) -> Server:
     return Server(h)
 
 
-def tl_submit(srv: Server, lat: Lattice, f, u, **opts) -> int:
+def tl_submit(srv: Server, lat: Lattice, f, u, stream=None, **opts) -> int:
+    """Queue a solve; its kernels wait for the work enqueued on `stream` (torch's
+    current stream by default) before the call."""
     shape = (lat.ny, lat.nx, 2)
     o = make_opts(**opts)
     ticket = C.c_uint64()
     st = load().tl_submit(srv.handle, lat.handle, C.c_void_p(_dev_ptr(f, "f", shape)),
-                          C.c_void_p(_dev_ptr(u, "u", shape)), C.byref(o), C.byref(ticket))
+                          C.c_void_p(_dev_ptr(u, "u", shape)), C.byref(o),
+                          C.c_void_p(_stream_ptr(stream)), C.byref(ticket))
     if st != TL_OK:
         raise TLError(st, "tl_submit")
     srv._keep[ticket.value] = (lat, f, u)

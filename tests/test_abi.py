@@ -53,6 +53,8 @@ def test_strerror_is_total():
     (8, 8, {"ea": "neg"}),                         # negative stiffness
     (8, 8, {"ea": "nan"}),                         # non-finite stiffness
     (8, 8, {"fixed": "one"}),                      # a single support cannot stop rotation
+    (8, 8, {"ea": "isolated"}),                    # a free node with no rod
+    (8, 8, {"ea": "collinear"}),                   # a free node held by horizontal rods only
 ])
 def test_create_rejects_bad_descriptors_on_host(nx, ny, kw):
     tl, lib = _lib()
@@ -62,6 +64,12 @@ def test_create_rejects_bad_descriptors_on_host(nx, ny, kw):
         ea[1, 2, 3] = -1.0
     if kw.get("ea") == "nan":
         ea[0, 1, 1] = np.nan
+    if kw.get("ea") in ("isolated", "collinear"):
+        # the six rods of node (i, j) = (3, 3): its three forward rods and the
+        # forward rods of (2, 3), (3, 2) and (4, 2) that end on it ([d, j, i])
+        ea[1, 3, 3] = ea[1, 2, 3] = ea[2, 3, 3] = ea[2, 2, 4] = 0.0
+        if kw["ea"] == "isolated":
+            ea[0, 3, 3] = ea[0, 3, 2] = 0.0
     if kw.get("fixed") == "one":
         fixed = np.zeros((ny, nx), np.uint8)
         fixed[0, 0] = 1
@@ -75,7 +83,7 @@ def test_null_arguments_are_rejected():
     assert lib.tl_lattice_create(None, None, None) == tl.TL_E_INVAL
     assert lib.tl_solve(None, None, None, None, None, None) == tl.TL_E_INVAL
     assert lib.tl_poll(None, 0, None) == tl.TL_E_INVAL
-    assert lib.tl_submit(None, None, None, None, None, None) == tl.TL_E_INVAL
+    assert lib.tl_submit(None, None, None, None, None, None, None) == tl.TL_E_INVAL
     out = C.c_void_p()
     assert lib.tl_server_create(0, 1, C.byref(out)) == tl.TL_E_INVAL
     assert lib.tl_server_create(1 << 20, 0, C.byref(out)) == tl.TL_E_INVAL
