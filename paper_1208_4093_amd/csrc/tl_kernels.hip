@@ -463,6 +463,13 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     rz_part += (double)(rr[k].x * pp[k].x + rr[k].y * pp[k].y);
   }
   double rz = block_sum<NW>(rz_part, sred[0]);
+  // The sweeps end early, uniformly across the workgroup, when the PCG has
+  // nothing left to gain: p.Kp <= 0, or r.z has fallen below 2^-60 of its
+  // start in float32 (2^-120 in float64), far past the precision's attainable
+  // accuracy.  Past that point the recurrences of a small region run on
+  // underflowing values, and in float32 they can diverge after a thousand or
+  // so further sweeps.  The default sweep counts never reach the threshold.
+  const double rz_stop = rz * (sizeof(T) == 4 ? 0x1p-60 : 0x1p-120);
   for (int it = 0; it < A.inner_iters; ++it) {
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -504,7 +511,8 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       pq_part += (double)(pa.x * qx + pa.y * qy);
     }
     const double pq = block_sum<NW>(pq_part, sred[1]);
-    const T alpha = pq > 0.0 ? (T)(rz / pq) : (T)0;
+    if (!(pq > 0.0)) break;
+    const T alpha = (T)(rz / pq);
     double rzn_part = 0.0;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -521,6 +529,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       pp[k].x = qq[k].x + beta * pp[k].x;
       pp[k].y = qq[k].y + beta * pp[k].y;
     }
+    if (!(rz > rz_stop)) break;
   }
 
   // 4. store the relaxation increment on the set's own nodes (mode 7 as
