@@ -218,6 +218,22 @@ void tl_server_destroy(tl_server* srv);
 
 const char* tl_strerror(tl_status s);
 
+/* tl_solve without any device or host allocation, for callers that cannot
+ * allocate (code that must not call hipMalloc, tight serving loops, harnesses
+ * that forbid allocation).  The solve state lives in a fixed, library-owned
+ * device array of TL_NOALLOC_SCRATCH_BYTES per GPU (held until the process
+ * ends), which every tl_solve_noalloc call on that GPU reuses: calls on one
+ * GPU are serialised internally, and the array keeps the last call's
+ * contents (everything a solve reads is cleared by the solve itself).
+ * Results are bit for bit those of tl_solve.  Returns TL_E_BUDGET, before
+ * touching the device, when the lattice's solve state for opts (the
+ * solve_bytes of tl_lattice_facts, with max_iters + 1 history entries) exceeds
+ * the array; TL_E_INVAL for opts->profile or opts->trace (both would need
+ * allocations).  info->ms is host wall time.  The lattice itself was
+ * allocated by tl_lattice_create. */
+#define TL_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+tl_status tl_solve_noalloc(tl_lattice* lat, const double* f_dev, double* u_dev,
+                           const tl_opts* opts, tl_info* info, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -22,8 +22,11 @@ TL_FP64, TL_MIXED = 0, 1
 EXPORTS = (
     "tl_lattice_create", "tl_lattice_destroy", "tl_lattice_get_facts", "tl_solve",
     "tl_solve_batch", "tl_residual", "tl_server_create", "tl_submit", "tl_poll",
-    "tl_server_destroy", "tl_strerror",
+    "tl_server_destroy", "tl_strerror", "tl_solve_noalloc",
 )
+
+# Size of the fixed device array behind tl_solve_noalloc (TL_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class LatticeDesc(C.Structure):
@@ -95,6 +98,8 @@ def load():
         lib.tl_server_destroy.restype = None
         lib.tl_strerror.argtypes = [C.c_int]
         lib.tl_strerror.restype = C.c_char_p
+        lib.tl_solve_noalloc.argtypes = [P, P, P, C.POINTER(Opts), C.POINTER(Info), P]
+        lib.tl_solve_noalloc.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -240,6 +245,22 @@ def tl_solve(lat: Lattice, f, u, stream=None, check=True, **opts):
                          C.c_void_p(_stream_ptr(stream)))
     if check and st != TL_OK:
         raise TLError(st, "tl_solve")
+    out = info.as_dict()
+    out["status"] = st
+    return out
+
+
+def tl_solve_noalloc(lat: Lattice, f, u, stream=None, check=True, **opts):
+    """tl_solve with the solve state in the library's fixed device array (no
+    allocation).  Same arguments and result as tl_solve."""
+    shape = (lat.ny, lat.nx, 2)
+    o = make_opts(**opts)
+    info = Info()
+    st = load().tl_solve_noalloc(lat.handle, C.c_void_p(_dev_ptr(f, "f", shape)),
+                                 C.c_void_p(_dev_ptr(u, "u", shape)), C.byref(o), C.byref(info),
+                                 C.c_void_p(_stream_ptr(stream)))
+    if check and st != TL_OK:
+        raise TLError(st, "tl_solve_noalloc")
     out = info.as_dict()
     out["status"] = st
     return out

@@ -84,6 +84,7 @@ def test_null_arguments_are_rejected():
     assert lib.tl_solve(None, None, None, None, None, None) == tl.TL_E_INVAL
     assert lib.tl_poll(None, 0, None) == tl.TL_E_INVAL
     assert lib.tl_submit(None, None, None, None, None, None, None) == tl.TL_E_INVAL
+    assert lib.tl_solve_noalloc(None, None, None, None, None, None) == tl.TL_E_INVAL
     out = C.c_void_p()
     assert lib.tl_server_create(0, 1, C.byref(out)) == tl.TL_E_INVAL
     assert lib.tl_server_create(1 << 20, 0, C.byref(out)) == tl.TL_E_INVAL
