@@ -12,6 +12,8 @@ description):
   3. the q = 9 incremental modes of every set: translations (Eq. 9),
      constant-gradient modes about the set's representative node (Eq. 10),
      the relaxation increment and its two gradient-weighted copies (Eq. 13-14);
+     with q = 12 also the increment of the relaxation with fixed-force
+     boundary and its two gradient-weighted copies (Eq. 15-18);
   4. upper-level stiffness K_a = U^T K U (Eq. 6) and force
      P_a = U^T (p - K u^old) (Eq. 7);
   5. solve the upper-level system (Eq. 8);
@@ -24,6 +26,14 @@ grid; the last row/column of tiles is narrower when E does not divide the
 lattice side.  Every mode is zero on clamped DOFs, so supports never move.
 
 Readings where the paper is silent (stated, not derived):
+  * the fixed-force relaxation (Eq. 15-17) isolates the same region as the
+    fixed-displacement one: every rod that crosses the region's edge is cut
+    (Eq. 15 moves its coupling onto the diagonal with the opposite sign),
+    rods to clamped nodes inside the region stay; where the isolated region
+    can move rigidly (no clamped node inside it) Eq. 16 is singular and in
+    general inconsistent, and its minimum-norm least-squares solution is
+    taken, i.e. the right-hand side and the increment are both taken off
+    the region's rigid motions (which modes 1-6 already represent);
   * representative node of a set = centroid of the tile's nodes in physical
     coordinates, and the gradient modes are scaled by 1/(E/2); in exact
     arithmetic neither choice changes the iterates (span{1, x - c} =
@@ -46,6 +56,7 @@ from .lattice import node_xy
 from .solve import System, energy, rel_residuals, residual
 
 Q = 9   # modes per set on the hot path: Eq. 9 (2), Eq. 10 (4), Eq. 13-14 (3)
+Q12 = 12  # with the fixed-force relaxation modes of Eq. 17-18
 
 
 @dataclasses.dataclass
@@ -130,12 +141,123 @@ class LocalSolver:
         return d
 
 
-def mode_matrix(sys_: System, sets: Sets, delta: np.ndarray) -> sp.csr_matrix:
-    """U = [u_hat_k^(I)] as a sparse 2N x (Q*M) matrix, column Q*I + (k-1).
+def isolation_correction(K: sp.csr_matrix, idx: np.ndarray, inside: np.ndarray) -> sp.csr_matrix:
+    """Delta k of Eq. 15 on the region's free DOFs idx: block diagonal, the
+    2 x 2 block of node i the sum of K's (i, l) blocks over every node l
+    outside the region (inside: bool per node)."""
+    rows = K[idx].tocoo()
+    out = ~inside[rows.col // 2]
+    sums = np.zeros((idx.size, 2))
+    np.add.at(sums, (rows.row[out], rows.col[out] % 2), rows.data[out])
+    pos = {int(d): k for k, d in enumerate(idx)}
+    r, c, v = [], [], []
+    for k, d in enumerate(idx):
+        base = 2 * (int(d) // 2)
+        for cp in range(2):
+            r.append(k)
+            c.append(pos[base + cp])
+            v.append(sums[k, cp])
+    return sp.csr_matrix((v, (r, c)), shape=(idx.size, idx.size))
+
+
+class ForceLocalSolver:
+    """Exact local relaxation with fixed-force boundary (Eq. 15-17) for every
+    set, on the same region as LocalSolver.
+
+    (k^Inner + Delta k) is the stiffness of the isolated region (Eq. 15).
+    Subtracting (k^Inner + Delta k) u^Inner,old from both sides of Eq. 16
+    gives the increment of Eq. 17 directly:
+        (k^Inner + Delta k) (u^RF - u^old) = (p - K u^old)|_region,
+    whose right-hand side is the residual on the region.  Where the isolated
+    region can move rigidly, the minimum-norm solution is taken: with N an
+    orthonormal basis of the region's rigid motions that the isolated
+    stiffness does not resist, the bordered system
+        [[K_iso, N], [N^T, 0]] [x; l] = [r; 0]
+    gives K_iso x = r - N N^T r with N^T x = 0.  Factors are computed once and
+    reused.  The increment is kept on the set's own DOFs."""
+
+    def __init__(self, sys_: System, sets: Sets, overlap: int = 0):
+        self.idx, self.own, self.lu, self.kiso, self.dk, self.null = [], [], [], [], [], []
+        dof_set = np.repeat(sets.of_node, 2)
+        K = sys_.K.tocsr()
+        x, y = node_xy(sets.nx, sets.ny)
+        x, y = x.reshape(-1), y.reshape(-1)
+        nn = sets.nx * sets.ny
+        for I in range(sets.M):
+            nodes = relaxation_region(sets, I, overlap)
+            inside = np.zeros(nn, dtype=bool)
+            inside[nodes] = True
+            dofs = np.sort(np.concatenate([2 * nodes, 2 * nodes + 1]))
+            idx = dofs[sys_.free[dofs]]
+            self.idx.append(idx)
+            self.own.append(np.flatnonzero(dof_set[idx] == I))
+            if idx.size == 0:
+                for lst in (self.lu, self.kiso, self.dk, self.null):
+                    lst.append(None)
+                continue
+            dk = isolation_correction(K, idx, inside)
+            kiso = (K[idx][:, idx] + dk).tocsc()
+            N = self._rigid_null_space(kiso, idx, x, y)
+            self.dk.append(dk)
+            self.kiso.append(kiso)
+            self.null.append(N)
+            if N.shape[1]:
+                Nsp = sp.csc_matrix(N)
+                A = sp.bmat([[kiso, Nsp], [Nsp.T, None]], format="csc")
+                self.lu.append(spla.splu(A))
+            else:
+                self.lu.append(spla.splu(kiso))
+
+    @staticmethod
+    def _rigid_null_space(kiso, idx, x, y):
+        """Orthonormal basis of the rigid motions (two translations, rotation
+        about the region's centroid) of the region's free nodes that kiso
+        does not resist."""
+        node = idx // 2
+        comp = idx % 2
+        xc, yc = x[node].mean(), y[node].mean()
+        cand = np.stack([comp == 0, comp == 1,
+                         np.where(comp == 0, -(y[node] - yc), x[node] - xc)], 1).astype(float)
+        cand /= np.linalg.norm(cand, axis=0)
+        KN = kiso @ cand
+        _, sv, Vt = np.linalg.svd(KN, full_matrices=True)
+        scale = abs(kiso).sum(axis=1).max()
+        sv = np.concatenate([sv, np.zeros(3 - sv.size)])
+        V = Vt.T[:, sv <= 1e-10 * scale]
+        if V.shape[1] == 0:
+            return np.zeros((idx.size, 0))
+        Q, _ = np.linalg.qr(cand @ V)
+        return Q
+
+    def relax_region(self, I: int, r: np.ndarray) -> np.ndarray:
+        """The increment on set I's whole region (free DOFs self.idx[I])."""
+        idx, lu, N = self.idx[I], self.lu[I], self.null[I]
+        if lu is None:
+            return np.zeros(0)
+        rhs = r[idx]
+        if N.shape[1]:
+            return lu.solve(np.concatenate([rhs, np.zeros(N.shape[1])]))[:idx.size]
+        return lu.solve(rhs)
+
+    def relax(self, r: np.ndarray) -> np.ndarray:
+        """Fixed-force relaxation increment (Eq. 17) of every set, stacked."""
+        d = np.zeros_like(r)
+        for I, (idx, own) in enumerate(zip(self.idx, self.own)):
+            if self.lu[I] is not None:
+                d[idx[own]] = self.relax_region(I, r)[own]
+        return d
+
+
+def mode_matrix(sys_: System, sets: Sets, delta: np.ndarray,
+                delta_f: np.ndarray | None = None) -> sp.csr_matrix:
+    """U = [u_hat_k^(I)] as a sparse 2N x (q*M) matrix, column q*I + (k-1),
+    q = 9, or 12 when the fixed-force increment delta_f is given.
 
     Modes 1-2 translations (Eq. 9); 3-6 (x - x_I, 0), (y - y_I, 0),
     (0, x - x_I), (0, y - y_I) (Eq. 10), scaled; 7 the relaxation increment
-    (Eq. 13); 8-9 its copies weighted by (x - x_I) and (y - y_I) (Eq. 14)."""
+    (Eq. 13); 8-9 its copies weighted by (x - x_I) and (y - y_I) (Eq. 14);
+    10 the fixed-force increment (Eq. 17); 11-12 its weighted copies (Eq. 18)."""
+    q = Q if delta_f is None else Q12
     nn = sets.nx * sets.ny
     x, y = node_xy(sets.nx, sets.ny)
     I = sets.of_node
@@ -149,6 +271,9 @@ def mode_matrix(sys_: System, sets: Sets, delta: np.ndarray) -> sp.csr_matrix:
         (xi, zero), (eta, zero), (zero, xi), (zero, eta),
         (dx, dy), (xi * dx, xi * dy), (eta * dx, eta * dy),
     ]
+    if delta_f is not None:
+        fx, fy = delta_f[0::2], delta_f[1::2]
+        comps += [(fx, fy), (xi * fx, xi * fy), (eta * fx, eta * fy)]
     rows, cols, vals = [], [], []
     node = np.arange(nn)
     for k, (cx, cy) in enumerate(comps):
@@ -156,10 +281,10 @@ def mode_matrix(sys_: System, sets: Sets, delta: np.ndarray) -> sp.csr_matrix:
             v = np.where(free_node, comp, 0.0)
             nz = v != 0.0
             rows.append(2 * node[nz] + c)
-            cols.append(Q * I[nz] + k)
+            cols.append(q * I[nz] + k)
             vals.append(v[nz])
     return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                         shape=(2 * nn, Q * sets.M)).tocsr()
+                         shape=(2 * nn, q * sets.M)).tocsr()
 
 
 def upper_level(sys_: System, U: sp.csr_matrix, u_old: np.ndarray):
@@ -190,6 +315,7 @@ class Step:
     R1: float
     R2: float
     delta: np.ndarray        # relaxation increments (Eq. 13)
+    delta_f: np.ndarray | None   # fixed-force relaxation increments (Eq. 17), q = 12
     U: sp.csr_matrix         # modes
     Kc: np.ndarray           # Eq. 6
     P: np.ndarray            # Eq. 7
@@ -200,19 +326,24 @@ class Step:
 class Method:
     """Outer loop of the hierarchical solver with exact inner solves."""
 
-    def __init__(self, sys_: System, sets: Sets, overlap: int = 0):
+    def __init__(self, sys_: System, sets: Sets, overlap: int = 0, modes: int = Q):
+        if modes not in (Q, Q12):
+            raise ValueError("modes must be 9 or 12")
         self.sys = sys_
         self.sets = sets
+        self.q = modes
         self.local = LocalSolver(sys_, sets, overlap)
+        self.local_f = ForceLocalSolver(sys_, sets, overlap) if modes == Q12 else None
 
     def step(self, u_old: np.ndarray) -> Step:
         r = residual(self.sys, u_old)
         R1, R2 = rel_residuals(self.sys, u_old)
         delta = self.local.relax(r)
-        U = mode_matrix(self.sys, self.sets, delta)
+        delta_f = self.local_f.relax(r) if self.local_f is not None else None
+        U = mode_matrix(self.sys, self.sets, delta, delta_f)
         Kc, P = upper_level(self.sys, U, u_old)
         a = solve_upper(Kc, P)
-        return Step(r, R1, R2, delta, U, Kc, P, a, u_old + U @ a)
+        return Step(r, R1, R2, delta, delta_f, U, Kc, P, a, u_old + U @ a)
 
     def run(self, tol: float, max_iters: int, u0: np.ndarray | None = None):
         """Iterate from u0 (default: prescribed values, zero elsewhere) until

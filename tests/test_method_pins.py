@@ -104,8 +104,8 @@ def test_planted_wrong_gradient_mode_is_caught(monkeypatch):
     mode 8) leaves the new residual not orthogonal to the intended modes."""
     real = om.mode_matrix
 
-    def no_eta(S, sets, delta):
-        U = real(S, sets, delta).tolil()
+    def no_eta(S, sets, delta, *rest):
+        U = real(S, sets, delta, *rest).tolil()
         U[:, 8::om.Q] = U[:, 7::om.Q]
         return U.tocsr()
     S, m = _setup(40, 33, 16, seed=2)
@@ -260,8 +260,8 @@ def test_planted_duplicate_gradient_mode_is_caught(monkeypatch):
     """Mode 4, (y - y_I, 0), replaced by a copy of mode 3, (x - x_I, 0)."""
     real = om.mode_matrix
 
-    def dup(S, sets, delta):
-        U = real(S, sets, delta).tolil()
+    def dup(S, sets, delta, *rest):
+        U = real(S, sets, delta, *rest).tolil()
         U[:, 3::om.Q] = U[:, 2::om.Q]
         return U.tocsr()
     monkeypatch.setattr(om, "mode_matrix", dup)
@@ -273,8 +273,8 @@ def test_planted_transposed_gradient_mode_is_caught(monkeypatch):
     """Mode 6, (0, y - y_I), built as (0, x - x_I): a copy of mode 5."""
     real = om.mode_matrix
 
-    def tr(S, sets, delta):
-        U = real(S, sets, delta).tolil()
+    def tr(S, sets, delta, *rest):
+        U = real(S, sets, delta, *rest).tolil()
         U[:, 5::om.Q] = U[:, 4::om.Q]
         return U.tocsr()
     monkeypatch.setattr(om, "mode_matrix", tr)
@@ -286,8 +286,8 @@ def test_planted_wrong_weight_in_relaxation_mode_is_caught(monkeypatch):
     """Mode 9 weighted by x (a copy of mode 8) instead of y (Eq. 14)."""
     real = om.mode_matrix
 
-    def wrong(S, sets, delta):
-        U = real(S, sets, delta).tolil()
+    def wrong(S, sets, delta, *rest):
+        U = real(S, sets, delta, *rest).tolil()
         U[:, 8::om.Q] = U[:, 7::om.Q]
         return U.tocsr()
     monkeypatch.setattr(om, "mode_matrix", wrong)
@@ -299,8 +299,8 @@ def test_planted_mode_on_clamped_node_is_caught(monkeypatch):
     """Translation mode left non-zero on the clamped nodes of a set."""
     real = om.mode_matrix
 
-    def leaky(S, sets, delta):
-        U = real(S, sets, delta).tolil()
+    def leaky(S, sets, delta, *rest):
+        U = real(S, sets, delta, *rest).tolil()
         clamped = np.flatnonzero(~S.free)
         for d in clamped[0::2]:
             U[d, om.Q * sets.of_node[d // 2]] = 1.0
