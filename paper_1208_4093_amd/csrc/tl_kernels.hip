@@ -2142,6 +2142,11 @@ hipError_t launch_blockinv_batch(const BatchEntry* B, const int* set_lat, int ns
   return hipGetLastError();
 }
 
+// Co-resident workgroups of the fused upper-level kernel at `lds` bytes of
+// dynamic LDS: the occupancy per CU times the CUs, or at most the value of
+// TL_COARSE_BATCH_WG when set (for runs under tools that can keep part of the
+// device from a kernel, such as hardware counter collection; a lattice's own
+// workgroup count and with it its results do not change).
 int coarse_batch_capacity(size_t lds) {
   static bool attr_set = false;
   if (!attr_set) {
@@ -2161,7 +2166,10 @@ int coarse_batch_capacity(size_t lds) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_coarse_batch, COARSE_NT,
                                                    lds) != hipSuccess)
     return 0;
-  return per_cu * cus;
+  int cap = per_cu * cus;
+  const char* v = getenv("TL_COARSE_BATCH_WG");
+  if (v && *v && atoi(v) > 0) cap = std::min(cap, atoi(v));
+  return cap;
 }
 
 hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, int nwg, size_t lds,
