@@ -218,6 +218,55 @@ void tl_server_destroy(tl_server* srv);
 
 const char* tl_strerror(tl_status s);
 
+/* Autotuning of the launch choices of a lattice shape: the set edge E of the
+ * partition into sets (section 2.2), the overlap of the relaxation region
+ * (section 2.2 end) and the relaxation sweeps per set (the inner solve of
+ * Eq. 12).  A process-wide table maps a shape key and a precision to one
+ * choice.  The key is (round(2 log2 nx), round(2 log2 ny)): lattices whose
+ * sides fall in the same half-octaves share an entry.  The table is read from
+ * the text file named by the environment variable TL_TUNE_CACHE at its first
+ * use (a missing file is an empty table), and tl_tune rewrites that file after
+ * every measurement.
+ *
+ * How the library applies it: tl_lattice_create with set_edge = 0 takes the
+ * set edge of the shape's mixed-precision entry, else of its float64 entry,
+ * else the built-in rule.  A solve (tl_solve, tl_solve_batch, tl_submit,
+ * tl_solve_noalloc) whose opts leave overlap or inner_iters at 0 takes them
+ * from the entry of the lattice's shape and the solve's precision when that
+ * entry's set edge is the lattice's, else the built-in defaults.  The choice
+ * depends on the lattice's shape and the precision alone, so a lattice's
+ * batched and served results stay bit for bit those of tl_solve alone, as
+ * long as the table does not change between the calls. */
+typedef struct {
+    int32_t set_edge;          /* 16, 32 or 64; 0 = no entry                      */
+    int32_t overlap;           /* -1 (the set alone), 1, 2 or 4                    */
+    int32_t inner_iters;       /* relaxation sweeps per set                        */
+    int32_t nx, ny;            /* the lattice the choice was measured on           */
+    double ms;                 /* its measured solve time                          */
+} tl_tune_entry;
+
+/* Measure candidate choices on the lattice of desc (arrays as for
+ * tl_lattice_create) with the load f_dev (device double [ny][nx][2]) in
+ * opts->precision to opts->rtol (other opts fields as for tl_solve; overlap,
+ * inner_iters and desc->set_edge are the searched quantities and ignored),
+ * and record the fastest choice that converged under the shape's key.  The
+ * search is coordinate-wise from the built-in defaults: the set edge over
+ * {16, 32, 64} (edges at most the lattice's longer side), then the overlap
+ * over {1, 2, 4}, then the sweeps over the default +-4 and +-8; each
+ * candidate is solved twice after a warm-up and timed by host wall clock
+ * (the faster of the two counts).  Allocates device memory for the candidate
+ * lattices and one displacement array; runs on hip_stream.  out receives the
+ * choice.  Returns TL_E_NOCONV when no candidate converged (nothing recorded). */
+tl_status tl_tune(const tl_lattice_desc* desc, const double* f_dev, const tl_opts* opts,
+                  tl_tune_entry* out, void* hip_stream);
+/* The table's entry for a shape and precision (out->set_edge = 0: none). */
+tl_status tl_tune_lookup(int32_t nx, int32_t ny, tl_precision precision, tl_tune_entry* out);
+/* Merge the entries of a table file into the table (TL_E_INVAL on a malformed
+ * file, nothing merged), write the table to a file, or empty it. */
+tl_status tl_tune_load(const char* path);
+tl_status tl_tune_save(const char* path);
+tl_status tl_tune_clear(void);
+
 /* tl_solve without any device or host allocation, for callers that cannot
  * allocate (code that must not call hipMalloc, tight serving loops, harnesses
  * that forbid allocation).  The solve state lives in a fixed, library-owned

@@ -591,6 +591,7 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
     j.f = f_dev[i];
     j.u = u_dev[i];
     j.o = o;
+    apply_tuned(j.L, &j.o);
     j.lock_lattice = false;
     pending.push_back(&j);
   }
@@ -658,6 +659,7 @@ tl_status tl_submit(tl_server* S, tl_lattice* L, const double* f_dev, double* u_
   j->f = f_dev;
   j->u = u_dev;
   if (resolve_opts(opts, &j->o) != TL_OK) { delete j; return TL_E_INVAL; }
+  apply_tuned(L, &j->o);
   j->o.trace = nullptr;
   j->o.profile = 0;
   if (job_bytes(j) > S->budget || !coresident({j})) { delete j; return TL_E_BUDGET; }

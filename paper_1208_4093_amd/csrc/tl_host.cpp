@@ -185,6 +185,8 @@ tl_status resolve_opts(const tl_opts* o, Opts* r) {
   r->warm = o ? o->warm_start : 0;
   r->trace = o ? o->trace : nullptr;
   r->profile = o ? o->profile : 0;
+  r->overlap_default = !o || o->overlap == 0;
+  r->inner_default = !o || o->inner_iters == 0;
   if (!(r->rtol > 0.0) || r->max_iters < 0 || r->inner < 0 || !tile_overlap_supported(r->overlap))
     return TL_E_INVAL;
   return TL_OK;
@@ -566,6 +568,10 @@ tl_status tl_lattice_create(const tl_lattice_desc* desc, void* hip_stream, tl_la
       for (size_t n = 0; n < 2 * nn; ++n)
         if (!std::isfinite(desc->u_fixed[n])) return TL_E_NONFINITE;
   }
+  // (the lookup also reads the tuning table's file on its first use, so that
+  // later solves on the lattice find the table in memory)
+  const int tuned_E = tuned_set_edge(nx, ny);
+  if (E == 0) E = tuned_E;
   if (E == 0) E = default_set_edge(nx, ny);
   hipStream_t st = (hipStream_t)hip_stream;
   tl_lattice* L = new (std::nothrow) tl_lattice();
@@ -715,6 +721,7 @@ tl_status tl_solve(tl_lattice* L, const double* f_dev, double* u_dev, const tl_o
   if (!L || !f_dev || !u_dev) return TL_E_INVAL;
   Opts o;
   if (resolve_opts(opts, &o) != TL_OK) return TL_E_INVAL;
+  apply_tuned(L, &o);
   std::lock_guard<std::mutex> lock(L->mu);
   tl_status err = TL_OK;
   Work* w = lattice_work(L, o.mixed, o.max_iters + 1, &err);

@@ -100,6 +100,9 @@ extern "C" tl_status tl_solve_noalloc(tl_lattice* L, const double* f_dev, double
   Opts o;
   if (resolve_opts(opts, &o) != TL_OK) return TL_E_INVAL;
   if (o.profile || o.trace) return TL_E_INVAL;
+  // tuned choices, as tl_solve takes them (the table was read from its file
+  // when the lattice was created: this lookup allocates nothing)
+  apply_tuned(L, &o);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return TL_E_DEVICE;
   if (dev != L->device || dev < 0 || dev >= kMaxDevices) return TL_E_INVAL;

@@ -48,6 +48,8 @@ struct Opts {
   int warm;
   tl_trace* trace;
   int profile;
+  bool overlap_default;  // the caller left overlap at 0 (library default or tuned)
+  bool inner_default;    // the caller left inner_iters at 0
 };
 
 }  // namespace tl
@@ -86,6 +88,13 @@ struct CoarseShape {
 };
 CoarseShape coarse_shape(const Geo& g);
 tl_status resolve_opts(const tl_opts* o, Opts* r);
+int default_inner_iters(int E, bool mixed);
+// Autotuning table (tl_tune.cpp): the tuned set edge of a shape (0: none),
+// and the tuned overlap and sweeps of the lattice's shape and the solve's
+// precision where the caller left them at 0 and the entry's set edge is the
+// lattice's.
+int tuned_set_edge(int nx, int ny);
+void apply_tuned(const tl_lattice* L, Opts* o);
 // Build the lattice's upper-level coarse space once (needs one solve state
 // just initialised by its init kernel); synchronises the stream.
 tl_status ensure_coarse_space(tl_lattice* L, Work* w, const Opts& o, const double* f,

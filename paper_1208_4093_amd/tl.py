@@ -22,7 +22,8 @@ TL_FP64, TL_MIXED = 0, 1
 EXPORTS = (
     "tl_lattice_create", "tl_lattice_destroy", "tl_lattice_get_facts", "tl_solve",
     "tl_solve_batch", "tl_residual", "tl_server_create", "tl_submit", "tl_poll",
-    "tl_server_destroy", "tl_strerror", "tl_solve_noalloc",
+    "tl_server_destroy", "tl_strerror", "tl_solve_noalloc", "tl_tune", "tl_tune_lookup",
+    "tl_tune_load", "tl_tune_save", "tl_tune_clear",
 )
 
 # Size of the fixed device array behind tl_solve_noalloc (TL_NOALLOC_SCRATCH_BYTES).
@@ -33,6 +34,14 @@ class LatticeDesc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("ea", C.c_void_p),
                 ("fixed", C.c_void_p), ("u_fixed", C.c_void_p),
                 ("set_edge", C.c_int32), ("ptrs_on_device", C.c_int32)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("set_edge", C.c_int32), ("overlap", C.c_int32), ("inner_iters", C.c_int32),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Trace(C.Structure):
@@ -100,6 +109,16 @@ def load():
         lib.tl_strerror.restype = C.c_char_p
         lib.tl_solve_noalloc.argtypes = [P, P, P, C.POINTER(Opts), C.POINTER(Info), P]
         lib.tl_solve_noalloc.restype = C.c_int
+        lib.tl_tune.argtypes = [C.POINTER(LatticeDesc), P, C.POINTER(Opts), C.POINTER(TuneEntry), P]
+        lib.tl_tune.restype = C.c_int
+        lib.tl_tune_lookup.argtypes = [C.c_int32, C.c_int32, C.c_int, C.POINTER(TuneEntry)]
+        lib.tl_tune_lookup.restype = C.c_int
+        lib.tl_tune_load.argtypes = [C.c_char_p]
+        lib.tl_tune_load.restype = C.c_int
+        lib.tl_tune_save.argtypes = [C.c_char_p]
+        lib.tl_tune_save.restype = C.c_int
+        lib.tl_tune_clear.argtypes = []
+        lib.tl_tune_clear.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -162,9 +181,9 @@ class Lattice:
             pass
 
 
-def tl_lattice_create(nx, ny, ea=None, fixed=None, u_fixed=None, set_edge=0, stream=None):
-    """Create a lattice from host numpy arrays (ea float32 [3, ny, nx], fixed
-    uint8 [ny, nx], u_fixed float64 [ny, nx, 2]) or device torch tensors."""
+def _lattice_desc(nx, ny, ea, fixed, u_fixed, set_edge):
+    """The tl_lattice_desc of host numpy arrays or device torch tensors, and
+    the arrays it points into (to be kept alive for the call)."""
     keep = []
     on_dev = None
 
@@ -203,6 +222,13 @@ def tl_lattice_create(nx, ny, ea=None, fixed=None, u_fixed=None, set_edge=0, str
     d.u_fixed = ptr(u_fixed, np.float64, (ny, nx, 2), "u_fixed")
     d.set_edge = int(set_edge)
     d.ptrs_on_device = 1 if on_dev else 0
+    return d, keep
+
+
+def tl_lattice_create(nx, ny, ea=None, fixed=None, u_fixed=None, set_edge=0, stream=None):
+    """Create a lattice from host numpy arrays (ea float32 [3, ny, nx], fixed
+    uint8 [ny, nx], u_fixed float64 [ny, nx, 2]) or device torch tensors."""
+    d, keep = _lattice_desc(nx, ny, ea, fixed, u_fixed, set_edge)
     h = C.c_void_p()
     st = load().tl_lattice_create(C.byref(d), C.c_void_p(_stream_ptr(stream)), C.byref(h))
     if st != TL_OK:
@@ -341,3 +367,47 @@ def tl_poll(srv: Server, ticket: int):
     if st != TL_PENDING:
         srv._keep.pop(ticket, None)
     return st, info.as_dict()
+
+
+# ---------------------------------------------------------------- autotuning
+
+def tl_tune(nx, ny, f, ea=None, fixed=None, u_fixed=None, stream=None, check=True, **opts):
+    """Measure launch choices for the lattice's shape and precision (opts as
+    for tl_solve; overlap and inner_iters are searched) and record the
+    fastest under the shape's key.  Returns the chosen entry as a dict."""
+    d, keep = _lattice_desc(nx, ny, ea, fixed, u_fixed, 0)
+    o = make_opts(**opts)
+    e = TuneEntry()
+    st = load().tl_tune(C.byref(d), C.c_void_p(_dev_ptr(f, "f", (ny, nx, 2))), C.byref(o),
+                        C.byref(e), C.c_void_p(_stream_ptr(stream)))
+    del keep
+    if check and st != TL_OK:
+        raise TLError(st, "tl_tune")
+    out = e.as_dict()
+    out["status"] = st
+    return out
+
+
+def tl_tune_lookup(nx, ny, precision=TL_FP64):
+    """The table's entry for a shape and precision, or None."""
+    e = TuneEntry()
+    st = load().tl_tune_lookup(int(nx), int(ny), int(precision), C.byref(e))
+    if st != TL_OK:
+        raise TLError(st, "tl_tune_lookup")
+    return e.as_dict() if e.set_edge else None
+
+
+def tl_tune_load(path):
+    st = load().tl_tune_load(os.fsencode(path))
+    if st != TL_OK:
+        raise TLError(st, "tl_tune_load")
+
+
+def tl_tune_save(path):
+    st = load().tl_tune_save(os.fsencode(path))
+    if st != TL_OK:
+        raise TLError(st, "tl_tune_save")
+
+
+def tl_tune_clear():
+    load().tl_tune_clear()

@@ -85,6 +85,10 @@ def test_null_arguments_are_rejected():
     assert lib.tl_poll(None, 0, None) == tl.TL_E_INVAL
     assert lib.tl_submit(None, None, None, None, None, None, None) == tl.TL_E_INVAL
     assert lib.tl_solve_noalloc(None, None, None, None, None, None) == tl.TL_E_INVAL
+    assert lib.tl_tune(None, None, None, None, None) == tl.TL_E_INVAL
+    assert lib.tl_tune_lookup(64, 64, 0, None) == tl.TL_E_INVAL
+    assert lib.tl_tune_load(None) == tl.TL_E_INVAL
+    assert lib.tl_tune_save(None) == tl.TL_E_INVAL
     out = C.c_void_p()
     assert lib.tl_server_create(0, 1, C.byref(out)) == tl.TL_E_INVAL
     assert lib.tl_server_create(1 << 20, 0, C.byref(out)) == tl.TL_E_INVAL
