@@ -174,9 +174,11 @@ tl_status tl_solve(tl_lattice* lat, const double* f_dev, double* u_dev,
  * tile launch per set edge over the sets of all lattices, one boundary-block
  * and one block-inverse launch over all sets, and one persistent upper-level
  * launch in which every lattice owns its own range of workgroups; chunks of
- * iterations are captured once in a hipGraph and replayed.  The lattices are
- * taken in order into groups whose upper-level workgroups fit co-resident on
- * the device; groups run one after another.  Each lattice's result is bit for
+ * iterations are captured once in a hipGraph and replayed.  The upper-level
+ * launch may hold more workgroups than fit the device at once (they take their
+ * places in start order, so a lattice whose workgroups have all started runs
+ * to its end); each lattice's own upper-level workgroups must fit at once
+ * (else TL_E_BUDGET).  Each lattice's result is bit for
  * bit the one tl_solve gives it alone (its kernels, set edge and reduction
  * orders depend on that lattice only).  infos[k] receives lattice k's result
  * (ms = wall time from the call's start until lattice k's finish was seen at
@@ -197,8 +199,7 @@ tl_status tl_residual(tl_lattice* lat, const double* f_dev, const double* u_dev,
 
 /* Continuous-batching server.  Requests are admitted in arrival order while
  * the device state of all admitted requests fits hbm_budget_bytes, fewer than
- * max_slots are admitted, and the upper-level workgroups of the admitted
- * requests of one precision fit co-resident; a background worker advances all
+ * max_slots are admitted; a background worker advances all
  * admitted requests of a precision together in fused launches, eight outer
  * iterations at a time, retires each as it converges and admits waiting
  * requests at once.  Results are bit for bit those of tl_solve alone.

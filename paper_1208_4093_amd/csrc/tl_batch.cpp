@@ -4,8 +4,9 @@
 // iteration of all of them is: one tile launch per set edge present (the
 // tiles of every lattice with that edge), one boundary-block launch and one
 // block-inverse launch over the sets of all lattices, and one persistent
-// upper-level launch in which each lattice owns a range of co-resident
-// workgroups and runs its own grid sums.  Every kernel reads its lattice's
+// upper-level launch in which each lattice owns a range of workgroups and
+// runs its own grid sums (the launch may exceed what fits the device at
+// once: workgroups take their places in start order).  Every kernel reads its lattice's
 // iteration counter and stop flag from device memory, so the launches of a
 // chunk of iterations have fixed arguments: tl_solve_batch captures one
 // chunk in a hipGraph and replays it.  Finished lattices' workgroups return
@@ -76,29 +77,36 @@ struct Job {
 // Workgroup plan of a fused upper-level launch.  Each lattice gets the
 // workgroup count of its single-lattice shape, which depends on the lattice
 // alone, so its grid-sum order, and with it every rounding, is the same alone
-// and in any batch.  All workgroups of the launch must be co-resident (each
-// lattice's grid sums wait on its own workgroups), so the plan picks an LDS
-// size class (64 KB: two workgroups per CU beside the static arrays; else
-// 152 KB: one) that every
-// lattice's unstaged slice fits, checks the total against the co-resident
-// capacity at that class, and enables LDS staging per lattice where it still
-// fits the class.  Returns false when the lattices cannot all be co-resident.
+// and in any batch.  The fused kernel hands out its workgroup indices in the
+// order the workgroups start (see k_coarse_batch), so the launch may exceed
+// the device's co-resident capacity when every lattice's own workgroups fit
+// one XCD's share of it; otherwise all of the launch's workgroups must fit
+// at once.  The plan picks an LDS size class (64 KB: two workgroups per CU
+// beside the static arrays; else 152 KB: one) that every lattice's unstaged
+// slice fits and at which one of those two conditions holds, and enables LDS
+// staging per lattice where it still fits the class.  Returns false when no
+// class qualifies.
+constexpr int kXcdCount = 8;   // XCDs the workgroups of a launch are dealt over
+
 bool plan_coarse(const std::vector<const Geo*>& gs, std::vector<int>* nw_out,
                  std::vector<CoarseShape>* shape_out, size_t* lds_out) {
   const int n = (int)gs.size();
   std::vector<CoarseShape> shape(n);
   std::vector<int> nw(n);
+  int largest = 0;
   long used = 0;
   for (int b = 0; b < n; ++b) {
     shape[b] = coarse_shape(*gs[b]);
     nw[b] = shape[b].nwg;
+    largest = std::max(largest, nw[b]);
     used += nw[b];
   }
   static const size_t classes[2] = {64 * 1024, COARSE_DYN_LDS_MAX};
   for (size_t cap : classes) {
     bool ok = true;
     for (int b = 0; b < n && ok; ++b) ok = coarse_lds_bytes(*gs[b], nw[b], 0, 0, shape[b].two_level) <= cap;
-    if (!ok || coarse_batch_capacity(cap) < used) continue;
+    const int fit = coarse_batch_capacity(cap);   // workgroups resident at once
+    if (!ok || !(used <= fit || largest <= fit / kXcdCount)) continue;
     size_t lds = 0;
     for (int b = 0; b < n; ++b) {
       const int vec = shape[b].vec_lds && coarse_lds_bytes(*gs[b], nw[b], 1, 0, shape[b].two_level) <= cap;
@@ -116,7 +124,7 @@ bool plan_coarse(const std::vector<const Geo*>& gs, std::vector<int>* nw_out,
   return false;
 }
 
-// True when the jobs' upper-level workgroups can all be co-resident.
+// True when every job's own upper-level workgroups can be resident at once.
 bool coresident(const std::vector<Job*>& jobs) {
   std::vector<const Geo*> gs;
   for (Job* j : jobs) gs.push_back(&j->L->g);
@@ -141,6 +149,8 @@ struct FusedBatch {
   int nsets = 0;
   int* d_wg_lat = nullptr;
   int nwg = 0;
+  int max_nwg = 0;              // the most upper-level workgroups of one lattice
+  unsigned* d_ticket = nullptr; // workgroup ticket counter of the fused upper-level kernel
   size_t lds = 0;
   Ctrl* d_ctrl = nullptr;       // gathered control blocks
   Ctrl* h_ctrl = nullptr;       // pinned
@@ -152,10 +162,11 @@ struct FusedBatch {
       if (d_tile_lat[k]) (void)hipFree(d_tile_lat[k]);
       d_tile_lat[k] = nullptr;
     }
-    for (void* p : {(void*)d_entries, (void*)d_set_lat, (void*)d_wg_lat})
+    for (void* p : {(void*)d_entries, (void*)d_set_lat, (void*)d_wg_lat, (void*)d_ticket})
       if (p) (void)hipFree(p);
     d_entries = nullptr;
     d_set_lat = d_wg_lat = nullptr;
+    d_ticket = nullptr;
   }
   void release() {
     release_tables();
@@ -208,6 +219,7 @@ struct FusedBatch {
       for (int w = 0; w < nw[b]; ++w) wl.push_back(b);
     }
     nwg = (int)wl.size();
+    max_nwg = nw.empty() ? 0 : *std::max_element(nw.begin(), nw.end());
     auto up = [&](const void* src, size_t bytes, void** dst) -> hipError_t {
       hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
       if (e == hipSuccess && bytes) e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st);
@@ -221,6 +233,8 @@ struct FusedBatch {
     }
     TB_TRY(up(sl.data(), sl.size() * sizeof(int), &p)); d_set_lat = (int*)p;
     TB_TRY(up(wl.data(), wl.size() * sizeof(int), &p)); d_wg_lat = (int*)p;
+    TB_TRY(hipMalloc(&p, sizeof(unsigned))); d_ticket = (unsigned*)p;
+    TB_TRY(hipMemsetAsync(d_ticket, 0, sizeof(unsigned), st));
     if (cap < n) {
       if (d_ctrl) (void)hipFree(d_ctrl);
       if (h_ctrl) (void)hipHostFree(h_ctrl);
@@ -248,7 +262,7 @@ struct FusedBatch {
     TB_TRY(launch_offdiag_batch(mixed, d_entries, d_set_lat, nsets, st));
     TB_TRY(launch_blockinv_batch(d_entries, d_set_lat, nsets, st));
     if (ev) TB_TRY(hipEventRecord(ev[kGroups + 1], st));
-    TB_TRY(launch_coarse_batch(d_entries, d_wg_lat, nwg, lds, st));
+    TB_TRY(launch_coarse_batch(d_entries, d_wg_lat, d_ticket, nwg, max_nwg, lds, st));
     if (ev) TB_TRY(hipEventRecord(ev[kGroups + 2], st));
     return TL_OK;
   }
@@ -323,7 +337,7 @@ struct BatchProfile {
 
 int edge_slot(int E) { return E == 16 ? 0 : E == 32 ? 1 : 2; }
 
-// Run one co-resident group of a tl_solve_batch call to completion: start
+// Run one group of a tl_solve_batch call to completion: start
 // every solve, build the fused tables, capture one chunk of iterations in a
 // hipGraph and replay it until every lattice of the group has stopped, then
 // copy out and certify each result (marking its job finished).  With a
@@ -474,7 +488,8 @@ void server_loop(tl_server* S) {
         Job* j = S->queue.front();
         const size_t b = job_bytes(j);
         if (S->used + b > S->budget) break;
-        // the fused batch of the job's precision must stay co-resident
+        // every lattice of the fused batch of the job's precision must keep
+        // its own upper-level workgroups resident at once
         std::vector<Job*> group;
         for (Job* k : live[j->o.mixed ? 1 : 0]) group.push_back(k);
         for (Job* k : admitted)
@@ -581,8 +596,9 @@ tl_status tl_solve_batch(int32_t n, tl_lattice* const* lats, const double* const
   (void)hipEventRecord(ev_in, user);
   (void)hipStreamWaitEvent(st, ev_in, 0);
   (void)hipEventRecord(e0, st);
-  // Lattices are taken in order into groups whose upper-level workgroups
-  // can all be co-resident; the groups run one after another.
+  // Lattices are taken in order into groups (one, unless adding a lattice
+  // moves the group to an LDS class at which some lattice's upper-level
+  // workgroups no longer fit at once); the groups run one after another.
   tl_status first = TL_OK;
   std::vector<Job*> pending;
   for (int i = 0; i < n; ++i) {

@@ -206,8 +206,11 @@ hipError_t launch_offdiag_batch(bool mixed, const BatchEntry* B, const int* set_
                                 hipStream_t stream);
 hipError_t launch_blockinv_batch(const BatchEntry* B, const int* set_lat, int nsets,
                                  hipStream_t stream);
-hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, int nwg, size_t lds,
-                               hipStream_t stream);
+// ticket: a device counter at 0 (the launch leaves it at 0); max_lattice_nwg:
+// the most workgroups any one lattice of the launch owns (at most the
+// co-resident capacity at lds, else hipErrorInvalidValue)
+hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, unsigned* ticket, int nwg,
+                               int max_lattice_nwg, size_t lds, hipStream_t stream);
 int coarse_batch_capacity(size_t lds);   // co-resident workgroups of the fused upper-level kernel
 hipError_t launch_gather_ctrl(const BatchEntry* B, int n, Ctrl* out, hipStream_t stream);
 hipError_t launch_group1(const Geo& g, const float* ea, const uint8_t* mask, double* g1,

@@ -441,55 +441,41 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   //    Float32 form: r is scaled by 2^-e (e from max|r|) before rounding.
   const double rm = sfin[10];
   const double scl = (sizeof(T) == 4 && rm > 0.0 && isfinite(rm)) ? ldexp(1.0, -ilogb(rm)) : 1.0;
-  // Per node only x, r, p, K p and 1/det B stay in registers across the
-  // sweep's barriers (register pressure): the 2x2 diagonal block B is rebuilt
-  // from the rod stiffnesses, z = B^-1 r = adj(B) r / det B is formed once
-  // per sweep and waits for the direction update in the K p slot.
-  T2 x[NPT], rr[NPT], pp[NPT], qq[NPT];
-  auto precond = [&](const int k, const T2 rv) {
-    const T ka = (T)kk[k][0] + (T)kk[k][3], kb = (T)kk[k][1] + (T)kk[k][4];
-    const T kc = (T)kk[k][2] + (T)kk[k][5];
-    const T Dxx = ka + (T)0.25 * (kb + kc), Dyy = (T)0.75 * (kb + kc);
-    const T Dxy = (T)(0.5 * kS3) * (kb - kc);
-    return mk2<T>(idet[k] * (Dyy * rv.x - Dxy * rv.y), idet[k] * (Dxx * rv.y - Dxy * rv.x));
-  };
-  double rz_part = 0.0;
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    x[k] = mk2<T>((T)0, (T)0);
-    const double2 rk = kResidLds ? (act[k] ? sres[t + k * NT] : make_double2(0.0, 0.0)) : r[k];
-    rr[k] = mk2<T>((T)(rk.x * scl), (T)(rk.y * scl));
-    pp[k] = precond(k, rr[k]);
-    rz_part += (double)(rr[k].x * pp[k].x + rr[k].y * pp[k].y);
-  }
-  double rz = block_sum<NW>(rz_part, sred[0]);
-  // The sweeps end early, uniformly across the workgroup, when the PCG has
-  // nothing left to gain: p.Kp <= 0, or r.z has fallen below 2^-60 of its
-  // start in float32 (2^-120 in float64), far past the precision's attainable
-  // accuracy.  Past that point the recurrences of a small region run on
-  // underflowing values, and in float32 they can diverge after a thousand or
-  // so further sweeps.  The default sweep counts never reach the threshold.
-  const double rz_stop = rz * (sizeof(T) == 4 ? 0x1p-60 : 0x1p-120);
-  for (int it = 0; it < A.inner_iters; ++it) {
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      if (!act[k]) continue;
-      const int n = t + k * NT;
-      sp[(n / R + 1) * W + (n % R + 1)] = pp[k];
-    }
-    __syncthreads();
-    double pq_part = 0.0;
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      if (!act[k]) { qq[k] = mk2<T>((T)0, (T)0); continue; }
-      const int n = t + k * NT;
-      const int c = (n / R + 1) * W + (n % R + 1);
-      const T2 pa = pp[k];
+  // The sweep comes in two forms with the same iterates in exact arithmetic.
+  // With float32 sets of up to 32 x 32 nodes it exchanges z through LDS in
+  // the barrier interval of r.z (two barriers a sweep); in float64 and with
+  // 64 x 64 sets that form holds more registers and spills, so there the
+  // direction p is exchanged (three barriers a sweep, no spill added).
+  constexpr bool kTwoBarrier = sizeof(T) == 4 && E <= 32;
+  T2 x[NPT];
+  if constexpr (kTwoBarrier) {
+    // Per node only x, r, p, K p and 1/det B stay in registers across the
+    // sweep's barriers (register pressure): the 2x2 diagonal block B is rebuilt
+    // from the rod stiffnesses, and z = B^-1 r = adj(B) r / det B goes straight
+    // to the LDS buffer.
+    //
+    // Two barriers per sweep.  The preconditioned residual z, not the search
+    // direction, is exchanged through LDS, in the same barrier interval as the
+    // partial sums of r.z; after that barrier beta is known, so the direction
+    // p = z + beta p and its product K p = K z + beta K p (the recurrence of
+    // the previous product) follow without a further exchange, and the second
+    // barrier is the one of p.Kp.  In exact arithmetic these are the iterates
+    // of plain PCG.
+    T2 rr[NPT], pp[NPT], qq[NPT];
+    auto precond = [&](const int k, const T2 rv) {
+      const T ka = (T)kk[k][0] + (T)kk[k][3], kb = (T)kk[k][1] + (T)kk[k][4];
+      const T kc = (T)kk[k][2] + (T)kk[k][5];
+      const T Dxx = ka + (T)0.25 * (kb + kc), Dyy = (T)0.75 * (kb + kc);
+      const T Dxy = (T)(0.5 * kS3) * (kb - kc);
+      return mk2<T>(idet[k] * (Dyy * rv.x - Dxy * rv.y), idet[k] * (Dxx * rv.y - Dxy * rv.x));
+    };
+    // k^Inner applied to the buffer at active node k (own value za)
+    auto apply_k = [&](const int k, const int c, const T2 za) {
       // (float64 form: the stiffnesses pass an empty asm so that each sweep
       //  converts them afresh instead of the compiler holding the residual
       //  step's conversions in registers across the relaxation)
       float kq[6];
-#pragma unroll
+  #pragma unroll
       for (int b = 0; b < 6; ++b) {
         kq[b] = kk[k][b];
         if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(kq[b]));
@@ -498,8 +484,8 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       const T kc = (T)kq[2] + (T)kq[5];
       const T Dxx = ka + (T)0.25 * (kb + kc), Dyy = (T)0.75 * (kb + kc);
       const T Dxy = (T)(0.5 * kS3) * (kb - kc);
-      T qx = Dxx * pa.x + Dxy * pa.y;
-      T qy = Dxy * pa.x + Dyy * pa.y;
+      T qx = Dxx * za.x + Dxy * za.y;
+      T qy = Dxy * za.x + Dyy * za.y;
       T2 pb; T s;
       pb = sp[c + 1];     s = (T)kq[0] * pb.x;                                qx -= s;
       pb = sp[c - 1];     s = (T)kq[3] * pb.x;                                qx -= s;
@@ -507,29 +493,161 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       pb = sp[c - W];     s = (T)kq[4] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
       pb = sp[c + W - 1]; s = (T)kq[2] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
       pb = sp[c - W + 1]; s = (T)kq[5] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
-      qq[k] = mk2<T>(qx, qy);
-      pq_part += (double)(pa.x * qx + pa.y * qy);
-    }
-    const double pq = block_sum<NW>(pq_part, sred[1]);
-    if (!(pq > 0.0)) break;
-    const T alpha = (T)(rz / pq);
-    double rzn_part = 0.0;
-#pragma unroll
+      return mk2<T>(qx, qy);
+    };
+    auto cell = [&](const int k) { const int n = t + k * NT; return (n / R + 1) * W + (n % R + 1); };
+    // z = B^-1 r into the buffer; returns this thread's part of r.z
+    auto publish_z = [&]() {
+      double part = 0.0;
+  #pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        const T2 z = precond(k, rr[k]);
+        if (act[k]) sp[cell(k)] = z;
+        part += (double)(rr[k].x * z.x + rr[k].y * z.y);
+      }
+      return part;
+    };
+    // p = z + beta p, K p = K z + beta K p; returns this thread's part of p.Kp
+    auto next_direction = [&](const T beta) {
+      double part = 0.0;
+  #pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        if (!act[k]) { pp[k] = qq[k] = mk2<T>((T)0, (T)0); continue; }
+        const int c = cell(k);
+        const T2 z = sp[c];
+        const T2 w = apply_k(k, c, z);
+        pp[k].x = z.x + beta * pp[k].x;  pp[k].y = z.y + beta * pp[k].y;
+        qq[k].x = w.x + beta * qq[k].x;  qq[k].y = w.y + beta * qq[k].y;
+        part += (double)(pp[k].x * qq[k].x + pp[k].y * qq[k].y);
+      }
+      return part;
+    };
+  #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      x[k].x += alpha * pp[k].x;  x[k].y += alpha * pp[k].y;
-      rr[k].x -= alpha * qq[k].x; rr[k].y -= alpha * qq[k].y;
-      qq[k] = precond(k, rr[k]);
-      rzn_part += (double)(rr[k].x * qq[k].x + rr[k].y * qq[k].y);
+      x[k] = mk2<T>((T)0, (T)0);
+      pp[k] = qq[k] = mk2<T>((T)0, (T)0);
+      const double2 rk = kResidLds ? (act[k] ? sres[t + k * NT] : make_double2(0.0, 0.0)) : r[k];
+      rr[k] = mk2<T>((T)(rk.x * scl), (T)(rk.y * scl));
     }
-    const double rzn = block_sum<NW>(rzn_part, sred[it & 1 ? 0 : 2]);
-    const T beta = rz > 0.0 ? (T)(rzn / rz) : (T)0;
-    rz = rzn;
-#pragma unroll
+    double rz = block_sum<NW>(publish_z(), sred[0]);
+    // The sweeps end early, uniformly across the workgroup, when the PCG has
+    // nothing left to gain: p.Kp <= 0, or r.z has fallen below 2^-60 of its
+    // start in float32 (2^-120 in float64), far past the precision's attainable
+    // accuracy.  Past that point the recurrences of a small region run on
+    // underflowing values, and in float32 they can diverge after a thousand or
+    // so further sweeps.  The default sweep counts never reach the threshold.
+    const double rz_stop = rz * (sizeof(T) == 4 ? 0x1p-60 : 0x1p-120);
+    double pq = block_sum<NW>(next_direction((T)0), sred[1]);
+    for (int it = 0; it < A.inner_iters; ++it) {
+      if (!(pq > 0.0)) break;
+      const T alpha = (T)(rz / pq);
+  #pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        x[k].x += alpha * pp[k].x;  x[k].y += alpha * pp[k].y;
+        rr[k].x -= alpha * qq[k].x; rr[k].y -= alpha * qq[k].y;
+      }
+      if (it + 1 == A.inner_iters) break;
+      // (the buffer is free: every read of it as z came before the last p.Kp
+      //  barrier; likewise the slots of each sum before the other's barrier)
+      const double rzn = block_sum<NW>(publish_z(), sred[0]);
+      if (!(rzn > rz_stop)) break;
+      const T beta = rz > 0.0 ? (T)(rzn / rz) : (T)0;
+      rz = rzn;
+      pq = block_sum<NW>(next_direction(beta), sred[1]);
+    }
+
+  } else {
+    // Per node only x, r, p, K p and 1/det B stay in registers across the
+    // sweep's barriers (register pressure): the 2x2 diagonal block B is rebuilt
+    // from the rod stiffnesses, z = B^-1 r = adj(B) r / det B is formed once
+    // per sweep and waits for the direction update in the K p slot.
+    T2 rr[NPT], pp[NPT], qq[NPT];
+    auto precond = [&](const int k, const T2 rv) {
+      const T ka = (T)kk[k][0] + (T)kk[k][3], kb = (T)kk[k][1] + (T)kk[k][4];
+      const T kc = (T)kk[k][2] + (T)kk[k][5];
+      const T Dxx = ka + (T)0.25 * (kb + kc), Dyy = (T)0.75 * (kb + kc);
+      const T Dxy = (T)(0.5 * kS3) * (kb - kc);
+      return mk2<T>(idet[k] * (Dyy * rv.x - Dxy * rv.y), idet[k] * (Dxx * rv.y - Dxy * rv.x));
+    };
+    double rz_part = 0.0;
+  #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      pp[k].x = qq[k].x + beta * pp[k].x;
-      pp[k].y = qq[k].y + beta * pp[k].y;
+      x[k] = mk2<T>((T)0, (T)0);
+      const double2 rk = kResidLds ? (act[k] ? sres[t + k * NT] : make_double2(0.0, 0.0)) : r[k];
+      rr[k] = mk2<T>((T)(rk.x * scl), (T)(rk.y * scl));
+      pp[k] = precond(k, rr[k]);
+      rz_part += (double)(rr[k].x * pp[k].x + rr[k].y * pp[k].y);
     }
-    if (!(rz > rz_stop)) break;
+    double rz = block_sum<NW>(rz_part, sred[0]);
+    // The sweeps end early, uniformly across the workgroup, when the PCG has
+    // nothing left to gain: p.Kp <= 0, or r.z has fallen below 2^-60 of its
+    // start in float32 (2^-120 in float64), far past the precision's attainable
+    // accuracy.  Past that point the recurrences of a small region run on
+    // underflowing values, and in float32 they can diverge after a thousand or
+    // so further sweeps.  The default sweep counts never reach the threshold.
+    const double rz_stop = rz * (sizeof(T) == 4 ? 0x1p-60 : 0x1p-120);
+    for (int it = 0; it < A.inner_iters; ++it) {
+  #pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        if (!act[k]) continue;
+        const int n = t + k * NT;
+        sp[(n / R + 1) * W + (n % R + 1)] = pp[k];
+      }
+      __syncthreads();
+      double pq_part = 0.0;
+  #pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        if (!act[k]) { qq[k] = mk2<T>((T)0, (T)0); continue; }
+        const int n = t + k * NT;
+        const int c = (n / R + 1) * W + (n % R + 1);
+        const T2 pa = pp[k];
+        // (float64 form: the stiffnesses pass an empty asm so that each sweep
+        //  converts them afresh instead of the compiler holding the residual
+        //  step's conversions in registers across the relaxation)
+        float kq[6];
+  #pragma unroll
+        for (int b = 0; b < 6; ++b) {
+          kq[b] = kk[k][b];
+          if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(kq[b]));
+        }
+        const T ka = (T)kq[0] + (T)kq[3], kb = (T)kq[1] + (T)kq[4];
+        const T kc = (T)kq[2] + (T)kq[5];
+        const T Dxx = ka + (T)0.25 * (kb + kc), Dyy = (T)0.75 * (kb + kc);
+        const T Dxy = (T)(0.5 * kS3) * (kb - kc);
+        T qx = Dxx * pa.x + Dxy * pa.y;
+        T qy = Dxy * pa.x + Dyy * pa.y;
+        T2 pb; T s;
+        pb = sp[c + 1];     s = (T)kq[0] * pb.x;                                qx -= s;
+        pb = sp[c - 1];     s = (T)kq[3] * pb.x;                                qx -= s;
+        pb = sp[c + W];     s = (T)kq[1] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
+        pb = sp[c - W];     s = (T)kq[4] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
+        pb = sp[c + W - 1]; s = (T)kq[2] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+        pb = sp[c - W + 1]; s = (T)kq[5] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+        qq[k] = mk2<T>(qx, qy);
+        pq_part += (double)(pa.x * qx + pa.y * qy);
+      }
+      const double pq = block_sum<NW>(pq_part, sred[1]);
+      if (!(pq > 0.0)) break;
+      const T alpha = (T)(rz / pq);
+      double rzn_part = 0.0;
+  #pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        x[k].x += alpha * pp[k].x;  x[k].y += alpha * pp[k].y;
+        rr[k].x -= alpha * qq[k].x; rr[k].y -= alpha * qq[k].y;
+        qq[k] = precond(k, rr[k]);
+        rzn_part += (double)(rr[k].x * qq[k].x + rr[k].y * qq[k].y);
+      }
+      const double rzn = block_sum<NW>(rzn_part, sred[it & 1 ? 0 : 2]);
+      const T beta = rz > 0.0 ? (T)(rzn / rz) : (T)0;
+      rz = rzn;
+  #pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        pp[k].x = qq[k].x + beta * pp[k].x;
+        pp[k].y = qq[k].y + beta * pp[k].y;
+      }
+      if (!(rz > rz_stop)) break;
+    }
+
   }
 
   // 4. store the relaxation increment on the set's own nodes (mode 7 as
@@ -1671,13 +1789,34 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(Geo g, CoarseArgs A) {
   coarse_body<true>(g, A, blockIdx.x, gridDim.x);
 }
 
-// Fused launch: lattice b owns workgroups [wg0, wg0 + nwg) and runs its own
-// grid sums among them; the launch is sized to be co-resident.
-// (two workgroups per CU, so that fused batches keep their co-resident capacity)
+// Fused launch: lattice b owns workgroups [wg0, wg0 + nwg) of the launch and
+// runs its own grid sums among them.  A workgroup's place in that order is
+// not its blockIdx but a ticket drawn when it starts, so the k-th workgroup
+// to start serves launch-wide index k.  The launch may then hold more
+// workgroups than fit the device at once: every lattice whose indices were
+// all handed out has all of its workgroups running and finishes without
+// waiting on anything else, so slots keep freeing until the one lattice
+// that is partly started gets the rest of its workgroups.  Workgroups are
+// dispatched to the XCDs round-robin by blockIdx, so the rest may all be
+// queued on one XCD; that XCD always frees a slot for them only if the
+// partly started lattice cannot fill it, so a launch that exceeds the
+// device holds lattices of at most one XCD's co-resident workgroups each
+// (the caller plans it so).  The workgroup that draws the last ticket resets
+// the counter for the next launch on the stream.
+// (two workgroups per CU: more lattices' upper levels run at once)
 __global__ __launch_bounds__(COARSE_NT, 2) void k_coarse_batch(const BatchEntry* __restrict__ B,
-                                                            const int* __restrict__ wg_lat) {
-  const BatchEntry& e = B[wg_lat[blockIdx.x]];
-  coarse_body<false>(e.g, e.ca, blockIdx.x - e.wg0, e.nwg);
+                                                            const int* __restrict__ wg_lat,
+                                                            unsigned* __restrict__ ticket) {
+  __shared__ int s_gw;
+  if (threadIdx.x == 0) {
+    const unsigned k = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (k + 1 == gridDim.x) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_gw = (int)k;
+  }
+  __syncthreads();
+  const int gw = s_gw;
+  const BatchEntry& e = B[wg_lat[gw]];
+  coarse_body<false>(e.g, e.ca, gw - e.wg0, e.nwg);
 }
 
 // ---------------------------------------------------------------------------
@@ -2172,11 +2311,11 @@ int coarse_batch_capacity(size_t lds) {
   return cap;
 }
 
-hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, int nwg, size_t lds,
-                               hipStream_t stream) {
+hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, unsigned* ticket, int nwg,
+                               int max_lattice_nwg, size_t lds, hipStream_t stream) {
   if (nwg <= 0) return hipSuccess;
-  if (coarse_batch_capacity(lds) < nwg) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_coarse_batch, dim3(nwg), dim3(COARSE_NT), lds, stream, B, wg_lat);
+  if (coarse_batch_capacity(lds) < max_lattice_nwg) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_coarse_batch, dim3(nwg), dim3(COARSE_NT), lds, stream, B, wg_lat, ticket);
   return hipGetLastError();
 }
 

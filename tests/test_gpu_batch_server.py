@@ -194,3 +194,57 @@ def test_server_admits_by_coresidency(big_mix):
         st, info = done[tk]
         assert st == tl.TL_OK
         assert torch.equal(u, ua)
+
+
+# Many lattices of 200 x 200 nodes with 16 x 16 sets: 169 sets, 11 upper-level
+# workgroups each, 616 in all, more than the device holds at once at two
+# workgroups per CU (512): the fused upper-level launch is over-subscribed
+# and its workgroups take their places in start order.
+MANY = 56
+
+
+@pytest.fixture(scope="module")
+def many_small():
+    lats, fs, alone = [], [], []
+    for k in range(MANY):
+        inst = make_instance(200, 200, seed=700 + k, ea="lognormal")
+        lats.append(tl.tl_lattice_create(200, 200, ea=inst.ea, fixed=inst.fixed, set_edge=16))
+        fs.append(torch.from_numpy(inst.f).cuda())
+    for lat, f in zip(lats, fs):
+        u = torch.zeros_like(f)
+        tl.tl_solve(lat, f, u, precision=1, rtol=1e-8)
+        alone.append(u)
+    return lats, fs, alone
+
+
+def test_oversubscribed_upper_level_batch_equals_alone(many_small):
+    lats, fs, alone = many_small
+    assert lats[0].sets == 169
+    us = [torch.zeros_like(f) for f in fs]
+    st, infos = tl.tl_solve_batch(lats, fs, us, precision=1, rtol=1e-8)
+    assert st == tl.TL_OK
+    for u, ua, info in zip(us, alone, infos):
+        assert info["status"] == tl.TL_OK
+        assert torch.equal(u, ua)
+
+
+def test_oversubscribed_server_equals_alone(many_small):
+    lats, fs, alone = many_small
+    srv = tl.tl_server_create(1 << 36, 64)
+    us = [torch.zeros_like(f) for f in fs]
+    tickets = [tl.tl_submit(srv, lat, f, u, precision=1, rtol=1e-8)
+               for lat, f, u in zip(lats, fs, us)]
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets) and time.time() - t0 < 100:
+        for tk in tickets:
+            if tk not in done:
+                st, info = tl.tl_poll(srv, tk)
+                if st != tl.TL_PENDING:
+                    done[tk] = (st, info)
+        time.sleep(0.001)
+    srv.close()
+    assert len(done) == len(tickets)
+    for tk, u, ua in zip(tickets, us, alone):
+        assert done[tk][0] == tl.TL_OK
+        assert torch.equal(u, ua)
