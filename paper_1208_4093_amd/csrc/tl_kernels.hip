@@ -209,10 +209,15 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   __shared__ double sred[3][NW];
   __shared__ double sacc[NW][KROW + 3];
   __shared__ double sfin[11];
-  // With 64 x 64 sets (four or more nodes per thread) the region's float64
-  // residual waits in LDS, not in registers, for the relaxation's start and
-  // the upper-level rows, when it fits beside the node buffer.
-  constexpr bool kResidLds = E >= 64 && (W * W + R * R) * 16 + 8192 <= 160 * 1024;
+  // The region's float64 residual waits in LDS, not in registers, for the
+  // relaxation's start and the upper-level rows, when it fits beside the
+  // node buffer: with 64 x 64 sets (four or more nodes per thread), and in
+  // the float64 form with 32 x 32 sets, whose tiles are held to 128
+  // registers so that two share a CU (1024^2: spill 112 -> 68 bytes per
+  // lane, launch 153 -> 148 us; the float32 tile gained nothing).
+  constexpr bool kResidLds = (E >= 64 || (E == 32 && sizeof(T) == 8)) &&
+                             (W * W + R * R) * 16 + 8192 <= 160 * 1024;
+  constexpr bool kLoadAhead = E >= 64;   // residual loads run ahead of the arithmetic
   __shared__ double2 sres[kResidLds ? R * R : 1];
   T2* sp = reinterpret_cast<T2*>(su);
 
@@ -322,18 +327,18 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   // the arithmetic (node k + kAhead's issued before node k's arithmetic),
   // fenced so the scheduler keeps that order: two with 256 registers per
   // thread (at most 512 threads), one with 128.
-  if constexpr (!kResidLds) {
+  if constexpr (!kLoadAhead) {
 #pragma unroll
     for (int k = 0; k < NPT; ++k) load_node(k);
   }
   constexpr int kAhead = NT <= 512 ? 2 : 1;
-  if constexpr (kResidLds) {
+  if constexpr (kLoadAhead) {
 #pragma unroll
     for (int k = 0; k < kAhead && k < NPT; ++k) load_node(k);
   }
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
-    if constexpr (kResidLds) {
+    if constexpr (kLoadAhead) {
       __builtin_amdgcn_sched_barrier(0);
       if (k + kAhead < NPT) load_node(k + kAhead);
     }
