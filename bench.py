@@ -87,6 +87,21 @@ def tile_bytes_per_node(mixed: bool) -> int:
     return 16 + 16 + 16 + 12 + 1 + (16 if mixed else 32)
 
 
+def band_factor_bytes(n: int, E: int, ov: int = 2) -> int:
+    """Bytes of band factor an exact-relaxation tile launch reads: every set's
+    region (its tile widened by ov nodes, clipped to the lattice) has 2 rw rh
+    DOFs, each a column of 2 R + 2 doubles (R = E + 2 ov), read once by the
+    forward and once by the backward triangular solve."""
+    R = E + 2 * ov
+    total = 0
+    for i0 in range(0, n, E):
+        rw = min(i0 + E + ov, n) - max(i0 - ov, 0)
+        for j0 in range(0, n, E):
+            rh = min(j0 + E + ov, n) - max(j0 - ov, 0)
+            total += 2 * (2 * rw * rh) * (2 * R + 2) * 8
+    return total
+
+
 T0 = time.perf_counter()
 
 
@@ -267,13 +282,16 @@ def run_single(args, wl, steps=None, warmup=None):
     u = torch.zeros_like(f)
     stream = torch.cuda.current_stream()
     bad = []
+    exact = getattr(args, "local_solve", "pcg") == "exact"
+    local = tl.TL_LOCAL_EXACT if exact else tl.TL_LOCAL_PCG
 
     def run_form(precision):
         mixed = precision == tl.TL_MIXED
         name = "mixed" if mixed else "fp64"
-        for w in range(warmup):
+        for w in range(warmup):   # the first exact solve also factors the regions
             u.zero_()
-            tl.tl_solve(lat, f, u, stream=stream, precision=precision, rtol=wl["rtol"])
+            tl.tl_solve(lat, f, u, stream=stream, precision=precision, rtol=wl["rtol"],
+                        local_solve=local)
         torch.cuda.synchronize()
         lat_ms, infos = [], []
         t0 = time.perf_counter()
@@ -281,7 +299,7 @@ def run_single(args, wl, steps=None, warmup=None):
             ts = time.perf_counter()
             u.zero_()
             info = tl.tl_solve(lat, f, u, stream=stream, check=False, precision=precision,
-                               rtol=wl["rtol"], profile=PROFILE_STRIDE)
+                               rtol=wl["rtol"], profile=PROFILE_STRIDE, local_solve=local)
             torch.cuda.synchronize()
             lat_ms.append(1000.0 * (time.perf_counter() - ts))
             infos.append(info)
@@ -295,9 +313,11 @@ def run_single(args, wl, steps=None, warmup=None):
         launches = sum(i["tile_launches"] for i in infos)
         tile_ms = sum(i["tile_ms"] for i in infos) / max(launches, 1)
         nodes = n * n
-        tile_gbs = tile_bytes_per_node(mixed) * nodes / (tile_ms * 1e-3) / 1e9
+        tile_bytes = tile_bytes_per_node(mixed) * nodes + (band_factor_bytes(n, E) if exact else 0)
+        tile_gbs = tile_bytes / (tile_ms * 1e-3) / 1e9
         u.zero_()
-        full = tl.tl_solve(lat, f, u, stream=stream, precision=precision, rtol=wl["rtol"], profile=1)
+        full = tl.tl_solve(lat, f, u, stream=stream, precision=precision, rtol=wl["rtol"], profile=1,
+                           local_solve=local)
         torch.cuda.synchronize()
         kern = {"tile": full["tile_ms"], "offdiag": full["offdiag_ms"], "coarse": full["coarse_ms"]}
         per_launch = {k: v / max(full["tile_launches"], 1) for k, v in kern.items()}
@@ -310,31 +330,37 @@ def run_single(args, wl, steps=None, warmup=None):
             "failed": len(infos) - len(ok),
             "kernel_ms_per_launch": per_launch,
             "kernel_share": {k: v / max(sum(kern.values()), 1e-30) for k, v in kern.items()},
-            "tile_gbs": tile_gbs, "tile_bytes_per_launch": tile_bytes_per_node(mixed) * nodes,
+            "tile_gbs": tile_gbs, "tile_bytes_per_launch": tile_bytes,
             "coarse_us_per_pcg_iteration": 1000.0 * full["coarse_ms"] / max(full["coarse_iters"], 1),
         }
 
     forms = [tl.TL_FP64, tl.TL_MIXED] if wl["headline"] == "fp64" else [tl.TL_MIXED, tl.TL_FP64]
     if args.headline_only:
         forms = forms[:1]
+    if exact:   # exact local solves exist in the float64 form only
+        forms = [tl.TL_FP64]
     res = {p: run_form(p) for p in forms}
     head = res[forms[0]]
     tile_ms = head["kernel_ms_per_launch"]["tile"]
     tb = wl.get("traffic_bytes")
     out = {
         "value": head["value"], "ms_per_step": head["ms_per_step"],
-        "dtype": "f64" if wl["headline"] == "fp64" else "f32+f64",
-        "config": {"workload": wl["desc"], "dof": inst.dof, "set_edge": E, "form": wl["headline"]},
+        "dtype": "f64" if wl["headline"] == "fp64" or exact else "f32+f64",
+        "config": {"workload": wl["desc"] + (", exact local solves" if exact else ""),
+                   "dof": inst.dof, "set_edge": E, "form": "fp64" if exact else wl["headline"],
+                   "local_solve": "exact" if exact else "pcg"},
         "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
         "iters": head["iters"], "coarse_iters": head["coarse_iters"], "rel_res": head["rel_res"],
         "failed": head["failed"], "kernel_ms_per_launch": head["kernel_ms_per_launch"],
         "kernel_share": head["kernel_share"],
         "coarse_us_per_pcg_iteration": head["coarse_us_per_pcg_iteration"],
         "roofline": {
-            "kernel": "k_tile (update + float64 residual + LDS relaxation + set rows of the upper level)",
+            "kernel": ("k_tile (update + float64 residual + exact relaxation with the band factor "
+                       "streamed from HBM + set rows of the upper level)" if exact else
+                       "k_tile (update + float64 residual + LDS relaxation + set rows of the upper level)"),
             "bound": "hbm", "achieved": head["tile_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": head["tile_gbs"] / HBM_PEAK_GBS,
-            "traffic": tb / (tile_ms * 1e-3) / 1e9 if tb else None,
+            "traffic": tb / (tile_ms * 1e-3) / 1e9 if tb and not exact else None,
             "avg_launch_us": 1000.0 * tile_ms,
             "algorithmic_bytes_per_launch": head["tile_bytes_per_launch"],
             "time_share": head["kernel_share"]["tile"],
@@ -575,7 +601,14 @@ def main():
     ap.add_argument("--lattices", type=int, default=256, help="batched workload: lattices per batch")
     ap.add_argument("--requests", type=int, default=80, help="served workload: requests per load")
     ap.add_argument("--max-slots", type=int, default=64, help="served workload: server slots")
+    ap.add_argument("--local-solve", choices=["pcg", "exact"], default="pcg",
+                    help="single-lattice workloads: relaxation by PCG sweeps, or exact with "
+                         "band Cholesky factors (float64 form only)")
     args = ap.parse_args()
+    if args.local_solve == "exact" and args.workload not in SINGLE:
+        print("--local-solve exact applies to the single-lattice workloads "
+              f"({', '.join(sorted(SINGLE))})", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the solver "
               "runs on a single MI355X and nothing in it uses a second GPU", file=sys.stderr)

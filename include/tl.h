@@ -118,6 +118,14 @@ typedef struct {
                                   nodes on every side, keeping the increment on the
                                   set (section 2.2 end): 1, 2 or 4; -1 = the set
                                   alone; 0 = library default (2)                    */
+    int32_t local_solve;       /* 0: the relaxation by inner_iters PCG sweeps (default);
+                                  1: exact (section 2.2 end: each set's region
+                                  stiffness k^Inner is factored once, band Cholesky,
+                                  on the first such solve of the lattice and
+                                  overlap, kept with the lattice and reused).  Float64
+                                  form only, sets of at most 32 x 32 nodes;
+                                  else TL_E_INVAL.  The factors take about
+                                  32 (E + 2w)^3 bytes per set                      */
 } tl_opts;
 
 typedef struct {

@@ -145,6 +145,7 @@ struct FusedBatch {
   static constexpr int kGroups = 12;
   int* d_tile_lat[kGroups] = {};
   int ntiles[kGroups] = {};
+  bool any_band[kGroups] = {};   // a lattice of the group solves its regions exactly
   int* d_set_lat = nullptr;
   int nsets = 0;
   int* d_wg_lat = nullptr;
@@ -189,6 +190,7 @@ struct FusedBatch {
     if (n == 0) return TL_OK;
     mixed = jobs[0]->o.mixed;
     h.assign(n, BatchEntry{});
+    for (bool& a : any_band) a = false;
     std::vector<int> tl[kGroups], sl;
     std::vector<const Geo*> gs(n);
     for (int b = 0; b < n; ++b) gs[b] = &jobs[b]->L->g;
@@ -209,6 +211,7 @@ struct FusedBatch {
       e.ca.vec_lds = shape[b].vec_lds;
       e.ca.blk_lds = shape[b].blk_lds;
       const int slot = group_slot(g.E, j->o.overlap);
+      if (e.ta.band) any_band[slot] = true;
       e.tile0 = (int)tl[slot].size();
       for (int t = 0; t < g.M; ++t) tl[slot].push_back(b);
       e.set0 = nsets;
@@ -256,7 +259,7 @@ struct FusedBatch {
     if (ev) TB_TRY(hipEventRecord(ev[0], st));
     for (int k = 0; k < kGroups; ++k) {
       TB_TRY(launch_tile_batch(mixed, kEdges[k / 4], kOverlaps[k % 4], d_entries, d_tile_lat[k],
-                               ntiles[k], st));
+                               ntiles[k], any_band[k], st));
       if (ev) TB_TRY(hipEventRecord(ev[1 + k], st));
     }
     TB_TRY(launch_offdiag_batch(mixed, d_entries, d_set_lat, nsets, st));
@@ -277,6 +280,7 @@ struct FusedBatch {
 };
 
 tl_status alloc_and_start(Job* j, hipStream_t st) {
+  if (tl_status s = ensure_band(j->L, j->o, st); s != TL_OK) return s;
   if (!j->w) {
     j->w = new (std::nothrow) Work();
     if (!j->w) return TL_E_NOMEM;

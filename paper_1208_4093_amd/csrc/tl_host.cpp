@@ -185,10 +185,13 @@ tl_status resolve_opts(const tl_opts* o, Opts* r) {
   r->warm = o ? o->warm_start : 0;
   r->trace = o ? o->trace : nullptr;
   r->profile = o ? o->profile : 0;
+  r->exact = o && o->local_solve == 1;
   r->overlap_default = !o || o->overlap == 0;
   r->inner_default = !o || o->inner_iters == 0;
   if (!(r->rtol > 0.0) || r->max_iters < 0 || r->inner < 0 || !tile_overlap_supported(r->overlap))
     return TL_E_INVAL;
+  if (o && (o->local_solve < 0 || o->local_solve > 1)) return TL_E_INVAL;
+  if (r->exact && r->mixed) return TL_E_INVAL;
   return TL_OK;
 }
 
@@ -208,6 +211,13 @@ void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const doub
   ta->ctrl = w->ctrl;
   ta->inner_iters = o.inner > 0 ? o.inner : default_inner_iters(L->g.E, o.mixed);
   ta->rhs_mode = L->ufix != nullptr;
+  {
+    const int R = L->g.E + 2 * o.overlap;
+    const int bi = o.overlap == 4 ? 3 : o.overlap;
+    ta->band = o.exact ? L->band[bi] : nullptr;
+    ta->band_stride = band_set_doubles(R);
+    ta->band_bs = band_bs(R);
+  }
   oa->d0 = w->d[0];
   oa->d1 = w->d[1];
   oa->off = w->off;
@@ -281,6 +291,31 @@ tl_status ensure_coarse_space(tl_lattice* L, Work* w, const Opts& o, const doubl
   TL_TRY(launch_agg_setup(L->g, L->g1, w->off, L->agg_xy, L->agg_sets, L->naggr, L->agg_inv, st));
   TL_TRY(hipStreamSynchronize(st));
   L->agg_ready = true;
+  return TL_OK;
+}
+
+tl_status ensure_band(tl_lattice* L, const Opts& o, hipStream_t st) {
+  if (!o.exact) return TL_OK;
+  if (o.mixed || L->g.E > 32) return TL_E_INVAL;
+  const int bi = o.overlap == 4 ? 3 : o.overlap;
+  std::lock_guard<std::mutex> lock(L->band_mu);
+  if (L->band[bi]) return TL_OK;
+  const int R = L->g.E + 2 * o.overlap;
+  void* p = nullptr;
+  const size_t bytes = band_set_doubles(R) * sizeof(double) * (size_t)L->g.M;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return TL_E_NOMEM;
+  }
+  hipError_t e = launch_band_factor(L->g, o.overlap, L->ea, L->mask, (double*)p, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return from_hip(e);
+  }
+  L->allocs.push_back(p);
+  L->bytes += bytes;
+  L->band[bi] = (double*)p;
   return TL_OK;
 }
 
@@ -723,7 +758,8 @@ tl_status tl_solve(tl_lattice* L, const double* f_dev, double* u_dev, const tl_o
   if (resolve_opts(opts, &o) != TL_OK) return TL_E_INVAL;
   apply_tuned(L, &o);
   std::lock_guard<std::mutex> lock(L->mu);
-  tl_status err = TL_OK;
+  tl_status err = ensure_band(L, o, (hipStream_t)hip_stream);
+  if (err != TL_OK) return err;
   Work* w = lattice_work(L, o.mixed, o.max_iters + 1, &err);
   if (!w) return err;
   return run_solve(L, w, o, f_dev, u_dev, info, (hipStream_t)hip_stream, w->ctrl_host, true);

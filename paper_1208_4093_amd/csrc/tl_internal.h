@@ -98,7 +98,23 @@ struct TileArgs {
   const Ctrl* ctrl;
   int inner_iters;
   int rhs_mode;          // 1: prescribed displacements present, norms use f - K_fc u_c
+  // exact local solve (float64 form): every set's band Cholesky factor of its
+  // region's k^Inner, BAND_CH-column chunks staged through dynamic LDS; null:
+  // preconditioned-CG sweeps
+  const double* band;
+  size_t band_stride;    // doubles per set
+  int band_bs;           // doubles per factor column (diagonal + lower band)
 };
+
+// Exact local solves: columns per LDS chunk of the band factor, and the
+// factor's shape for a relaxation region of at most R x R nodes (R = E + 2w):
+// n = 2 R^2 DOFs, lower bandwidth 2R + 1, so 2R + 2 doubles a column.
+constexpr int BAND_CH = 32;
+__host__ __device__ constexpr int band_bs(int R) { return 2 * R + 2; }
+__host__ __device__ constexpr size_t band_set_doubles(int R) { return (size_t)2 * R * R * band_bs(R); }
+__host__ __device__ constexpr size_t band_chunk_bytes(int R) {
+  return (size_t)2 * BAND_CH * band_bs(R) * sizeof(double);
+}
 
 struct CoarseArgs {
   const double* g1;      // [M][36]
@@ -201,7 +217,7 @@ hipError_t launch_agg_setup(const Geo& g, const double* g1, const double* off,
                             hipStream_t stream);
 // Fused launches over a batch (entries and lookup tables in device memory).
 hipError_t launch_tile_batch(bool mixed, int E, int ov, const BatchEntry* B, const int* tile_lat,
-                             int ntiles, hipStream_t stream);
+                             int ntiles, bool any_band, hipStream_t stream);
 hipError_t launch_offdiag_batch(bool mixed, const BatchEntry* B, const int* set_lat, int nsets,
                                 hipStream_t stream);
 hipError_t launch_blockinv_batch(const BatchEntry* B, const int* set_lat, int nsets,
@@ -213,6 +229,10 @@ hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, unsigned*
                                int max_lattice_nwg, size_t lds, hipStream_t stream);
 int coarse_batch_capacity(size_t lds);   // co-resident workgroups of the fused upper-level kernel
 hipError_t launch_gather_ctrl(const BatchEntry* B, int n, Ctrl* out, hipStream_t stream);
+// Band Cholesky factors of every set's relaxation region (overlap ov) into
+// band (band_set_doubles(E + 2 ov) doubles per set).
+hipError_t launch_band_factor(const Geo& g, int ov, const float* ea, const uint8_t* mask,
+                              double* band, hipStream_t stream);
 hipError_t launch_group1(const Geo& g, const float* ea, const uint8_t* mask, double* g1,
                          hipStream_t stream);
 hipError_t launch_init_state(const Geo& g, const uint8_t* mask, const double2* u_fixed,

@@ -185,6 +185,114 @@ template <> __device__ __forceinline__ double2 mk2<double>(double x, double y) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Exact local solve (section 2.2 end: the local stiffness matrices do not
+// change, so each is factored once and the factor reused).  A set's
+// relaxation region of rw x rh nodes has n = 2 rw rh DOFs in row-major node
+// order, x before y; a node's rods reach at most rw nodes ahead, so k^Inner
+// is a band matrix of lower bandwidth b = 2 rw + 1.  Clamped DOFs become
+// identity rows and columns (their residual is zero), so every region has a
+// positive definite matrix of the same shape.  The factor L (k^Inner = L L^T)
+// is stored column by column, BS doubles a column: 1/L_jj, then L_{j+1..j+b, j}.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BandRegion {
+  int ri0, rj0, rw, rh, n, b;
+};
+
+__device__ __forceinline__ BandRegion band_region(const Geo& g, int ov, int s) {
+  const int E = g.E, I = s % g.mx, J = s / g.mx;
+  const int i0 = I * E, j0 = J * E;
+  const int tw = min(E, g.nx - i0), th = min(E, g.ny - j0);
+  BandRegion r;
+  r.ri0 = max(i0 - ov, 0);
+  r.rj0 = max(j0 - ov, 0);
+  r.rw = min(i0 + tw + ov, g.nx) - r.ri0;
+  r.rh = min(j0 + th + ov, g.ny) - r.rj0;
+  r.n = 2 * r.rw * r.rh;
+  r.b = 2 * r.rw + 1;
+  return r;
+}
+
+// Entry (k + d, k), 0 <= d <= b, of the region's k^Inner (identity on clamped
+// DOFs; an identity column past the last DOF).
+__device__ double band_entry(const Geo& g, const float* __restrict__ ea,
+                             const uint8_t* __restrict__ mask, const BandRegion& br, int k, int d) {
+  if (k >= br.n) return d == 0 ? 1.0 : 0.0;
+  const int node = k >> 1, c = k & 1;
+  const int li = node % br.rw, lj = node / br.rw;
+  const size_t plane = (size_t)(g.ny + 2) * g.pitch;
+  const size_t p = pidx(g, br.ri0 + li, br.rj0 + lj);
+  if (mask[p]) return d == 0 ? 1.0 : 0.0;
+  if (d == 0 || (d == 1 && c == 0)) {
+    // the node's own 2x2 block: sum over its six rods of k n n^T
+    const double ka = (double)ea[p] + (double)ea[p - 1];
+    const double kb = (double)ea[plane + p] + (double)ea[plane + p - g.pitch];
+    const double kc = (double)ea[2 * plane + p] + (double)ea[2 * plane + p - g.pitch + 1];
+    if (d == 1) return 0.5 * kS3 * (kb - kc);
+    return c == 0 ? ka + 0.25 * (kb + kc) : 0.75 * (kb + kc);
+  }
+  const int r = k + d;
+  if (r >= br.n) return 0.0;
+  const int m = r >> 1, c2 = r & 1, delta = m - node;
+  // the forward neighbour at that DOF: east (+1), north-west (+rw - 1), north (+rw)
+  double kr, nx_, ny_;
+  int mi, mj;
+  if (delta == 1 && li + 1 < br.rw) {
+    kr = ea[p]; nx_ = 1.0; ny_ = 0.0; mi = li + 1; mj = lj;
+  } else if (delta == br.rw - 1 && li > 0 && lj + 1 < br.rh) {
+    kr = ea[2 * plane + p]; nx_ = -0.5; ny_ = kS3; mi = li - 1; mj = lj + 1;
+  } else if (delta == br.rw && lj + 1 < br.rh) {
+    kr = ea[plane + p]; nx_ = 0.5; ny_ = kS3; mi = li; mj = lj + 1;
+  } else {
+    return 0.0;
+  }
+  if (mask[pidx(g, br.ri0 + mi, br.rj0 + mj)]) return 0.0;
+  return -kr * (c2 == 0 ? nx_ : ny_) * (c == 0 ? nx_ : ny_);
+}
+
+}  // namespace
+
+// One workgroup per set: band Cholesky of its region's k^Inner, right-looking,
+// with the b + 1 columns still being updated in an LDS ring (dynamic LDS of
+// (b_max + 1) BS doubles); each column leaves the ring final and the next
+// enters assembled.
+__global__ __launch_bounds__(256) void k_band_factor(Geo g, int ov, const float* __restrict__ ea,
+                                                     const uint8_t* __restrict__ mask,
+                                                     double* __restrict__ band) {
+  extern __shared__ double ring[];
+  const int s = blockIdx.x, t = threadIdx.x;
+  const BandRegion br = band_region(g, ov, s);
+  const int R = g.E + 2 * ov, BS = band_bs(R);
+  const int n = br.n, b = br.b, nr = b + 1;
+  double* out = band + (size_t)s * band_set_doubles(R);
+  for (int e = t; e < nr * BS; e += 256) {
+    const int col = e / BS, d = e % BS;
+    ring[e] = d <= b ? band_entry(g, ea, mask, br, col, d) : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double* cj = ring + (size_t)(j % nr) * BS;
+    const double ljj = sqrt(cj[0]);
+    __syncthreads();   // every thread has read the pivot
+    for (int d = 1 + t; d <= b; d += 256) cj[d] /= ljj;
+    __syncthreads();
+    // A[j+a+e][j+a] -= L[j+a+e][j] L[j+a][j], 1 <= a <= b, 0 <= e <= b - a
+    for (int q = t; q < b * nr; q += 256) {
+      const int a = 1 + q / nr, e = q % nr;
+      if (e <= b - a) ring[(size_t)((j + a) % nr) * BS + e] -= cj[a + e] * cj[a];
+    }
+    __syncthreads();
+    // retire column j; column j + b + 1 takes its slot
+    for (int d = t; d < BS; d += 256) {
+      out[(size_t)j * BS + d] = d == 0 ? 1.0 / ljj : (d <= b ? cj[d] : 0.0);
+      cj[d] = d <= b ? band_entry(g, ea, mask, br, j + nr, d) : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Tile kernel: update + residual + local relaxation + set's upper-level rows.
 // ---------------------------------------------------------------------------
 //
@@ -453,7 +561,108 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   // direction p is exchanged (three barriers a sweep, no spill added).
   constexpr bool kTwoBarrier = sizeof(T) == 4 && E <= 32;
   T2 x[NPT];
-  if constexpr (kTwoBarrier) {
+  bool exact = false;
+  if constexpr (sizeof(T) == 8) {
+    if (A.band) {
+      // Exact local solve (section 2.2 end): k^Inner delta = r on the
+      // region with the set's band factor.  The residual goes to the node
+      // buffer in DOF order; wave 0 runs the two triangular solves column by
+      // column while the other waves stage the next chunk of factor columns
+      // into LDS.  Within wave 0 each column's LDS updates are seen by the
+      // next column's reads (one wave's LDS operations complete in order).
+      exact = true;
+      extern __shared__ double band_lds[];
+      constexpr int BS = band_bs(R);
+      const int n = 2 * rw * rh, b = 2 * rw + 1;
+      const double* Lg = A.band + (size_t)tile * A.band_stride;
+      double* v = reinterpret_cast<double*>(su);
+      auto residual_at = [&](const int k) -> double2 {
+        return kResidLds ? sres[t + k * NT] : r[k];
+      };
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        const int nn = t + k * NT, li = nn % R, lj = nn / R;
+        if (nn < R * R && li < rw && lj < rh) {
+          const double2 rk = act[k] ? residual_at(k) : make_double2(0.0, 0.0);
+          const int dof = 2 * (lj * rw + li);
+          v[dof] = rk.x;
+          v[dof + 1] = rk.y;
+        }
+      }
+      const int nch = (n + BAND_CH - 1) / BAND_CH;
+      auto load_chunk = [&](const int c, double* buf, const int t0, const int nth) {
+        const int j0 = c * BAND_CH, cols = min(BAND_CH, n - j0);
+        const double* src = Lg + (size_t)j0 * BS;
+        for (int e = t0; e < cols * BS; e += nth) buf[e] = src[e];
+      };
+      const int wave = t >> 6, lane = t & 63;
+      const int l1 = lane + 1, l2 = lane + 65;
+      double* buf0 = band_lds;
+      double* buf1 = band_lds + BAND_CH * BS;
+      // forward: L y = r
+      load_chunk(0, buf0, t, NT);
+      __syncthreads();
+      for (int c = 0; c < nch; ++c) {
+        const double* cur = (c & 1) ? buf1 : buf0;
+        if (wave != 0) {
+          if (c + 1 < nch) load_chunk(c + 1, (c & 1) ? buf0 : buf1, t - 64, NT - 64);
+        } else {
+          const int j0 = c * BAND_CH, j1 = min(n, j0 + BAND_CH);
+          for (int j = j0; j < j1; ++j) {
+            const double* col = cur + (j - j0) * BS;
+            const double yj = v[j] * col[0];
+            const double c1 = l1 <= b ? col[l1] : 0.0;
+            const double c2 = l2 <= b ? col[l2] : 0.0;
+            __builtin_amdgcn_wave_barrier();   // every lane has read v[j]
+            if (lane == 0) v[j] = yj;
+            if (l1 <= b && j + l1 < n) v[j + l1] -= c1 * yj;
+            if (l2 <= b && j + l2 < n) v[j + l2] -= c2 * yj;
+            __builtin_amdgcn_wave_barrier();   // the next column reads what this one wrote
+          }
+        }
+        __syncthreads();
+      }
+      // backward: L^T x = y
+      load_chunk(nch - 1, buf0, t, NT);
+      __syncthreads();
+      for (int cc = 0; cc < nch; ++cc) {
+        const int c = nch - 1 - cc;
+        const double* cur = (cc & 1) ? buf1 : buf0;
+        if (wave != 0) {
+          if (c > 0) load_chunk(c - 1, (cc & 1) ? buf0 : buf1, t - 64, NT - 64);
+        } else {
+          const int j0 = c * BAND_CH, j1 = min(n, j0 + BAND_CH);
+          for (int j = j1 - 1; j >= j0; --j) {
+            const double* col = cur + (j - j0) * BS;
+            double sum = 0.0;
+            if (l1 <= b && j + l1 < n) sum += col[l1] * v[j + l1];
+            if (l2 <= b && j + l2 < n) sum += col[l2] * v[j + l2];
+            sum = wave_sum(sum);
+            const double xj = (v[j] - sum) * col[0];
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) v[j] = xj;
+            __builtin_amdgcn_wave_barrier();
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        const int nn = t + k * NT, li = nn % R, lj = nn / R;
+        x[k] = mk2<T>((T)0, (T)0);
+        if (nn < R * R && li < rw && lj < rh && act[k]) {
+          const int dof = 2 * (lj * rw + li);
+          x[k] = mk2<T>((T)v[dof], (T)v[dof + 1]);
+        }
+      }
+      __syncthreads();   // every read of the buffer as v is done
+      for (int idx = t; idx < W * W; idx += NT) sp[idx] = mk2<T>((T)0, (T)0);
+      __syncthreads();
+    }
+  }
+  if (exact) {
+    // (the increment is in x)
+  } else if constexpr (kTwoBarrier) {
     // Per node only x, r, p, K p and 1/det B stay in registers across the
     // sweep's barriers (register pressure): the 2x2 diagonal block B is rebuilt
     // from the rod stiffnesses, and z = B^-1 r = adj(B) r / det B goes straight
@@ -2241,8 +2450,15 @@ hipError_t launch_tile(bool mixed, int ov, const Geo& g, const float* ea, const 
   const dim3 grid(g.M);
   const int E = g.E;
   const int nt = tile_threads(E, mixed, ov);
-#define TL_TILE(T, EE, NT, OV) \
-  hipLaunchKernelGGL((k_tile<T, EE, NT, OV>), grid, dim3(NT), 0, stream, g, ea, mask, a)
+  const size_t dyn = a.band ? band_chunk_bytes(E + 2 * ov) : 0;
+#define TL_TILE(T, EE, NT, OV)                                                                     \
+  do {                                                                                             \
+    if (dyn && hipFuncSetAttribute((const void*)k_tile<T, EE, NT, OV>,                             \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,                     \
+                                   (int)dyn) != hipSuccess)                                        \
+      return hipErrorInvalidValue;                                                                 \
+    hipLaunchKernelGGL((k_tile<T, EE, NT, OV>), grid, dim3(NT), dyn, stream, g, ea, mask, a);      \
+  } while (0)
   if (mixed) {
     TL_TILE_OVERLAPS(TL_TILE, float)
   } else {
@@ -2253,12 +2469,19 @@ hipError_t launch_tile(bool mixed, int ov, const Geo& g, const float* ea, const 
 }
 
 hipError_t launch_tile_batch(bool mixed, int E, int ov, const BatchEntry* B, const int* tile_lat,
-                             int ntiles, hipStream_t stream) {
+                             int ntiles, bool any_band, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   const dim3 grid(ntiles);
   const int nt = tile_threads(E, mixed, ov);
-#define TL_TILEB(T, EE, NT, OV) \
-  hipLaunchKernelGGL((k_tile_batch<T, EE, NT, OV>), grid, dim3(NT), 0, stream, B, tile_lat)
+  const size_t dyn = any_band ? band_chunk_bytes(E + 2 * ov) : 0;
+#define TL_TILEB(T, EE, NT, OV)                                                                    \
+  do {                                                                                             \
+    if (dyn && hipFuncSetAttribute((const void*)k_tile_batch<T, EE, NT, OV>,                       \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,                     \
+                                   (int)dyn) != hipSuccess)                                        \
+      return hipErrorInvalidValue;                                                                 \
+    hipLaunchKernelGGL((k_tile_batch<T, EE, NT, OV>), grid, dim3(NT), dyn, stream, B, tile_lat);   \
+  } while (0)
   if (mixed) {
     TL_TILE_OVERLAPS(TL_TILEB, float)
   } else {
@@ -2358,6 +2581,15 @@ hipError_t launch_coarse(const Geo& g, const CoarseArgs& a, hipStream_t stream) 
   const size_t lds = coarse_lds_bytes(g, a.nwg, a.vec_lds, a.blk_lds, a.naggr > 0);
   if (lds > COARSE_DYN_LDS_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_coarse, dim3(a.nwg), dim3(COARSE_NT), lds, stream, g, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_factor(const Geo& g, int ov, const float* ea, const uint8_t* mask,
+                              double* band, hipStream_t stream) {
+  const int R = g.E + 2 * ov;
+  const size_t lds = (size_t)(2 * R + 2) * band_bs(R) * sizeof(double);   // b_max + 1 columns
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_band_factor, dim3(g.M), dim3(256), lds, stream, g, ov, ea, mask, band);
   return hipGetLastError();
 }
 

@@ -99,7 +99,7 @@ extern "C" tl_status tl_solve_noalloc(tl_lattice* L, const double* f_dev, double
   if (!L || !f_dev || !u_dev) return TL_E_INVAL;
   Opts o;
   if (resolve_opts(opts, &o) != TL_OK) return TL_E_INVAL;
-  if (o.profile || o.trace) return TL_E_INVAL;
+  if (o.profile || o.trace || o.exact) return TL_E_INVAL;   // each would need allocations
   // tuned choices, as tl_solve takes them (the table was read from its file
   // when the lattice was created: this lookup allocates nothing)
   apply_tuned(L, &o);

@@ -48,6 +48,7 @@ struct Opts {
   int warm;
   tl_trace* trace;
   int profile;
+  bool exact;            // exact local solves with the lattice's band factors
   bool overlap_default;  // the caller left overlap at 0 (library default or tuned)
   bool inner_default;    // the caller left inner_iters at 0
 };
@@ -74,6 +75,10 @@ struct tl_lattice {
   int naggr = 0, agg_sets = 0, agg_g = 0, agg_nwg = 0;
   bool agg_ready = false;
   std::mutex agg_mu;
+  // band Cholesky factors of the sets' relaxation regions, by overlap 0, 1,
+  // 2, 4 (built on the first exact solve with that overlap)
+  double* band[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::mutex band_mu;
 };
 
 namespace tl {
@@ -94,6 +99,10 @@ int default_inner_iters(int E, bool mixed);
 // precision where the caller left them at 0 and the entry's set edge is the
 // lattice's.
 int tuned_set_edge(int nx, int ny);
+// The lattice's band factors for the solve's overlap, built on first use
+// (synchronises the stream when it builds them); TL_E_INVAL where exact
+// local solves are not supported (float32 form, 64 x 64 sets).
+tl_status ensure_band(tl_lattice* L, const Opts& o, hipStream_t st);
 void apply_tuned(const tl_lattice* L, Opts* o);
 // Build the lattice's upper-level coarse space once (needs one solve state
 // just initialised by its init kernel); synchronises the stream.

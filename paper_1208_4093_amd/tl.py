@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtl.so")
 TL_OK, TL_PENDING, TL_E_INVAL, TL_E_NOMEM, TL_E_NOCONV, TL_E_DEVICE, TL_E_BUDGET, TL_E_NONFINITE = \
     0, 1, -1, -2, -3, -4, -5, -6
 TL_FP64, TL_MIXED = 0, 1
+TL_LOCAL_PCG, TL_LOCAL_EXACT = 0, 1
 
 EXPORTS = (
     "tl_lattice_create", "tl_lattice_destroy", "tl_lattice_get_facts", "tl_solve",
@@ -54,7 +55,8 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int32),
                 ("inner_iters", C.c_int32), ("coarse_iters", C.c_int32),
                 ("coarse_rtol", C.c_double), ("warm_start", C.c_int32),
-                ("trace", C.POINTER(Trace)), ("profile", C.c_int32), ("overlap", C.c_int32)]
+                ("trace", C.POINTER(Trace)), ("profile", C.c_int32), ("overlap", C.c_int32),
+                ("local_solve", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -161,13 +163,21 @@ class Lattice:
     def __init__(self, handle, nx, ny):
         self.handle = handle
         self.nx, self.ny = nx, ny
+        f = self.facts()
+        self.set_edge, self.sets_x, self.sets_y, self.sets = (f["set_edge"], f["sets_x"],
+                                                              f["sets_y"], f["sets"])
+        self.dof, self.device_bytes = f["dof"], f["device_bytes"]
+        self.solve_bytes = f["solve_bytes"]
+
+    def facts(self):
+        """tl_lattice_get_facts now (device_bytes grows as solves add state)."""
         f = Facts()
-        st = load().tl_lattice_get_facts(handle, C.byref(f))
+        st = load().tl_lattice_get_facts(self.handle, C.byref(f))
         if st != TL_OK:
             raise TLError(st, "tl_lattice_get_facts")
-        self.set_edge, self.sets_x, self.sets_y, self.sets = f.set_edge, f.sets_x, f.sets_y, f.sets
-        self.dof, self.device_bytes = f.dof, f.device_bytes
-        self.solve_bytes = (f.solve_bytes[0], f.solve_bytes[1])
+        return dict(set_edge=f.set_edge, sets_x=f.sets_x, sets_y=f.sets_y, sets=f.sets,
+                    dof=f.dof, device_bytes=f.device_bytes,
+                    solve_bytes=(f.solve_bytes[0], f.solve_bytes[1]))
 
     def close(self):
         if self.handle:
@@ -237,7 +247,8 @@ def tl_lattice_create(nx, ny, ea=None, fixed=None, u_fixed=None, set_edge=0, str
 
 
 def make_opts(precision=TL_FP64, rtol=1e-8, max_iters=0, inner_iters=0, coarse_iters=0,
-              coarse_rtol=0.0, warm_start=False, trace=None, profile=False, overlap=0):
+              coarse_rtol=0.0, warm_start=False, trace=None, profile=False, overlap=0,
+              local_solve=0):
     o = Opts()
     o.precision = int(precision)
     o.rtol = float(rtol)
@@ -249,6 +260,7 @@ def make_opts(precision=TL_FP64, rtol=1e-8, max_iters=0, inner_iters=0, coarse_i
     o.trace = C.pointer(trace) if trace is not None else C.POINTER(Trace)()
     o.profile = int(profile)
     o.overlap = int(overlap)
+    o.local_solve = int(local_solve)
     return o
 
 

@@ -1,0 +1,242 @@
+"""Exact local solves (local_solve = 1) through the C ABI.
+
+The relaxation of section 2.2 solves k^Inner delta = r on every set's region
+exactly; the library factors each region's matrix once (band Cholesky) and
+reuses the factor (section 2.2 end).  With exact local solves and an upper
+level solved to 1e-15 the library follows the oracle's method model
+(oracle.method.Method: exact solves by sparse LU) step by step, so the
+float64 tolerances here are those of two different direct solvers on the
+same well-conditioned systems:
+
+* one outer iteration: increment, upper-level blocks and force against the
+  model, 1e-10 relative (2-norm per lattice); coefficients that solve the
+  model's upper-level system and the update they give, 1e-8 and 1e-9;
+* fifteen outer iterations: the per-iteration max(R1, R2) history against the
+  model's, within 5e-8 of the first entry;
+* solves to rtol 1e-10 against the oracle's direct solve, 1e-8 relative;
+* batched and served exact solves: bit for bit the solve alone;
+* the factors are built once per lattice and overlap, and counted in the
+  lattice's device bytes;
+* the float32 form, 64 x 64 sets and the allocation-free entry point reject
+  exact solves, as does a local_solve other than 0 or 1.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle.method as om
+from oracle.solve import solve, system_of
+from workloads import make_instance
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+tl = pytest.importorskip("paper_1208_4093_amd.tl")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def make_lattice(inst, E):
+    return tl.tl_lattice_create(inst.nx, inst.ny, ea=inst.ea, fixed=inst.fixed,
+                                u_fixed=inst.u_fixed, set_edge=E)
+
+
+def band_bytes(nx, ny, E, ov):
+    R = E + 2 * ov
+    M = -(-nx // E) * -(-ny // E)
+    return M * 2 * R * R * (2 * R + 2) * 8
+
+
+def ov_arg(ov):
+    return ov if ov > 0 else -1
+
+
+@pytest.mark.parametrize("nx,ny,E,ea,seed,ov", [
+    (40, 33, 16, "lognormal", 3, 2), (45, 37, 16, "unit", 4, 0), (70, 40, 32, "lognormal", 5, 1),
+    (64, 70, 32, "lognormal", 6, 4), (33, 70, 16, "lognormal", 7, 4), (96, 64, 32, "lognormal", 8, 2)])
+def test_one_iteration_exact_matches_method_model(nx, ny, E, ea, seed, ov):
+    inst = make_instance(nx, ny, seed=seed, ea=ea)
+    S = system_of(inst)
+    sets = om.make_sets(nx, ny, E)
+    step = om.Method(S, sets, overlap=ov).step(S.u_c.copy())
+    M, Q = sets.M, om.Q
+
+    def z(*shape):
+        return torch.zeros(shape, dtype=torch.float64, device="cuda")
+
+    tr = dict(delta=z(ny, nx, 2), kdiag=z(M, Q, Q), koff=z(M, 6, Q, Q), force=z(M, Q),
+              coef=z(M, Q), residual_history=z(4))
+    lat = make_lattice(inst, E)
+    f = dev(inst.f)
+    u = torch.zeros_like(f)
+    info = tl.tl_solve(lat, f, u, check=False, precision=tl.TL_FP64, rtol=1e-300, max_iters=1,
+                       coarse_iters=20000, coarse_rtol=1e-15, trace=tl.make_trace(**tr),
+                       overlap=ov_arg(ov), local_solve=tl.TL_LOCAL_EXACT)
+    torch.cuda.synchronize()
+    assert info["status"] == tl.TL_E_NOCONV and info["iters"] == 1
+
+    def rel(a, b):
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+    d_g = tr["delta"].cpu().numpy().reshape(-1)
+    assert rel(d_g, step.delta) <= 1e-10
+    P_g = tr["force"].cpu().numpy().reshape(-1)
+    assert rel(P_g, step.P) <= 1e-10
+    kd = tr["kdiag"].cpu().numpy()
+    for s in range(M):
+        want = step.Kc[Q * s:Q * s + Q, Q * s:Q * s + Q]
+        assert np.abs(kd[s] - want).max() <= 1e-10 * np.abs(want).max(), s
+    # the coefficients solve the upper-level system (unique only up to the null
+    # space of dependent modes, as on a set one node wide), and the update
+    # applies them (Eq. 3, 8)
+    a_g = tr["coef"].cpu().numpy().reshape(-1)
+    assert np.linalg.norm(step.Kc @ a_g - step.P) <= 1e-8 * np.linalg.norm(step.P)
+    assert rel(u.cpu().numpy().reshape(-1), step.u_new) <= 1e-9
+
+
+@pytest.mark.parametrize("nx,ny,E,ov", [(60, 45, 16, 2), (80, 70, 32, 1)])
+def test_exact_iteration_history_matches_method_model(nx, ny, E, ov):
+    inst = make_instance(nx, ny, seed=31, ea="lognormal")
+    S = system_of(inst)
+    sets = om.make_sets(nx, ny, E)
+    iters = 15
+    _, _, hist = om.Method(S, sets, overlap=ov).run(tol=0.0, max_iters=iters)
+    want = np.array([max(h[0], h[1]) for h in hist[:iters + 1]])
+    h_g = torch.zeros(iters + 1, dtype=torch.float64, device="cuda")
+    lat = make_lattice(inst, E)
+    f = dev(inst.f)
+    u = torch.zeros_like(f)
+    info = tl.tl_solve(lat, f, u, check=False, precision=tl.TL_FP64, rtol=1e-300,
+                       max_iters=iters, coarse_iters=20000, coarse_rtol=1e-15,
+                       trace=tl.make_trace(residual_history=h_g), overlap=ov_arg(ov),
+                       local_solve=tl.TL_LOCAL_EXACT)
+    torch.cuda.synchronize()
+    assert info["iters"] == iters
+    got = h_g.cpu().numpy()
+    assert want[-1] <= 0.1 * want[0]   # the history spans at least a decade
+    # a rounding difference du between the two solvers' iterates shows in the
+    # residual amplified by up to cond(K) ~ 1e5 here: bound the difference by
+    # the first residual, not entry by entry
+    assert np.all(np.abs(got - want) <= 5e-8 * want[0]), (got - want, want)
+
+
+@pytest.mark.parametrize("nx,ny,E,ov", [(200, 150, 32, 2), (130, 97, 16, 1), (150, 120, 16, 4),
+                                        (100, 100, 32, 0)])
+def test_exact_solve_matches_oracle(nx, ny, E, ov):
+    inst = make_instance(nx, ny, seed=40 + E + ov, ea="lognormal")
+    ref = solve(system_of(inst))
+    lat = make_lattice(inst, E)
+    f = dev(inst.f)
+    u = torch.zeros_like(f)
+    info = tl.tl_solve(lat, f, u, precision=tl.TL_FP64, rtol=1e-10, overlap=ov_arg(ov),
+                       local_solve=tl.TL_LOCAL_EXACT)
+    assert info["status"] == tl.TL_OK
+    err = np.linalg.norm(u.cpu().numpy().reshape(-1) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-8, err
+
+
+def test_factors_built_once_and_counted():
+    nx, ny, E = 90, 70, 16
+    inst = make_instance(nx, ny, seed=50, ea="lognormal")
+    lat = make_lattice(inst, E)
+    f = dev(inst.f)
+    before = lat.facts()["device_bytes"]
+    u1 = torch.zeros_like(f)
+    tl.tl_solve(lat, f, u1, precision=tl.TL_FP64, rtol=1e-10, overlap=2, local_solve=1)
+    after = lat.facts()["device_bytes"]
+    grown = after - before
+    # the first solve also allocates its per-solve state: the growth holds the
+    # factors (one set per overlap) and at most that state
+    assert grown >= band_bytes(nx, ny, E, 2)
+    u2 = torch.zeros_like(f)
+    tl.tl_solve(lat, f, u2, precision=tl.TL_FP64, rtol=1e-10, overlap=2, local_solve=1)
+    assert lat.facts()["device_bytes"] == after
+    assert torch.equal(u1, u2)
+    # another overlap: its own factors
+    u3 = torch.zeros_like(f)
+    tl.tl_solve(lat, f, u3, precision=tl.TL_FP64, rtol=1e-10, overlap=1, local_solve=1)
+    assert lat.facts()["device_bytes"] == after + band_bytes(nx, ny, E, 1)
+    # the relaxation by sweeps on the same lattice is unchanged by the factors
+    lat2 = make_lattice(inst, E)
+    u4 = torch.zeros_like(f)
+    u5 = torch.zeros_like(f)
+    tl.tl_solve(lat, f, u4, precision=tl.TL_FP64, rtol=1e-10, overlap=2)
+    tl.tl_solve(lat2, f, u5, precision=tl.TL_FP64, rtol=1e-10, overlap=2)
+    assert torch.equal(u4, u5)
+
+
+def test_exact_batch_and_served_equal_alone():
+    shapes = [(120, 90, 16, 2), (75, 140, 32, 2), (64, 64, 16, 2), (150, 60, 32, 1)]
+    insts = [make_instance(nx, ny, seed=60 + k, ea="lognormal") for k, (nx, ny, _, _) in
+             enumerate(shapes)]
+    lats = [make_lattice(i, E) for i, (_, _, E, _) in zip(insts, shapes)]
+    fs = [dev(i.f) for i in insts]
+    alone = []
+    for lat, f, (_, _, _, ov) in zip(lats, fs, shapes):
+        u = torch.zeros_like(f)
+        tl.tl_solve(lat, f, u, precision=tl.TL_FP64, rtol=1e-10, overlap=ov, local_solve=1)
+        alone.append(u)
+    # the batch takes one option set: lattices with overlap 2
+    pick = [k for k, s in enumerate(shapes) if s[3] == 2]
+    us = [torch.zeros_like(fs[k]) for k in pick]
+    st, _ = tl.tl_solve_batch([lats[k] for k in pick], [fs[k] for k in pick], us,
+                              precision=tl.TL_FP64, rtol=1e-10, overlap=2, local_solve=1)
+    assert st == tl.TL_OK
+    for k, u in zip(pick, us):
+        assert torch.equal(u, alone[k]), k
+    # a batch that mixes exact and sweep-relaxed lattices in one launch group
+    # is not possible (one option set per batch); a batch of fresh lattices
+    # builds their factors itself
+    fresh = [make_lattice(insts[k], shapes[k][2]) for k in pick]
+    us2 = [torch.zeros_like(fs[k]) for k in pick]
+    st, _ = tl.tl_solve_batch(fresh, [fs[k] for k in pick], us2, precision=tl.TL_FP64,
+                              rtol=1e-10, overlap=2, local_solve=1)
+    assert st == tl.TL_OK
+    for k, u in zip(pick, us2):
+        assert torch.equal(u, alone[k]), k
+    # served, each request with its own overlap
+    srv = tl.tl_server_create(8 << 30, 4)
+    try:
+        outs = [torch.zeros_like(f) for f in fs]
+        tickets = [tl.tl_submit(srv, lat, f, u, precision=tl.TL_FP64, rtol=1e-10, overlap=ov,
+                                local_solve=1)
+                   for lat, f, u, (_, _, _, ov) in zip(lats, fs, outs, shapes)]
+        t0 = time.time()
+        done = {}
+        while len(done) < len(tickets) and time.time() - t0 < 120:
+            for t in tickets:
+                if t not in done:
+                    st, info = tl.tl_poll(srv, t)
+                    if st != tl.TL_PENDING:
+                        done[t] = (st, info)
+            time.sleep(0.005)
+        assert len(done) == len(tickets)
+        for k, t in enumerate(tickets):
+            assert done[t][0] == tl.TL_OK
+            assert torch.equal(outs[k], alone[k]), k
+    finally:
+        srv.close()
+
+
+def test_exact_rejections():
+    inst = make_instance(80, 70, seed=70, ea="lognormal")
+    f = dev(inst.f)
+    u = torch.zeros_like(f)
+    lat16 = make_lattice(inst, 16)
+    st = tl.tl_solve(lat16, f, u, check=False, precision=tl.TL_MIXED, local_solve=1)["status"]
+    assert st == tl.TL_E_INVAL
+    st = tl.tl_solve(lat16, f, u, check=False, precision=tl.TL_FP64, local_solve=2)["status"]
+    assert st == tl.TL_E_INVAL
+    st = tl.tl_solve(lat16, f, u, check=False, precision=tl.TL_FP64, local_solve=-1)["status"]
+    assert st == tl.TL_E_INVAL
+    st = tl.tl_solve_noalloc(lat16, f, u, check=False, precision=tl.TL_FP64,
+                             local_solve=1)["status"]
+    assert st == tl.TL_E_INVAL
+    lat64 = make_lattice(inst, 64)
+    st = tl.tl_solve(lat64, f, u, check=False, precision=tl.TL_FP64, local_solve=1)["status"]
+    assert st == tl.TL_E_INVAL
+    # the rejected calls changed nothing: an exact solve still runs
+    info = tl.tl_solve(lat16, f, u, precision=tl.TL_FP64, rtol=1e-10, local_solve=1)
+    assert info["status"] == tl.TL_OK
