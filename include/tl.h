@@ -125,7 +125,7 @@ typedef struct {
                                   overlap, kept with the lattice and reused).  Float64
                                   form only, sets of at most 32 x 32 nodes;
                                   else TL_E_INVAL.  The factors take about
-                                  32 (E + 2w)^3 bytes per set                      */
+                                  64 (E + 2w)^3 bytes per set                      */
 } tl_opts;
 
 typedef struct {

@@ -99,21 +99,26 @@ struct TileArgs {
   int inner_iters;
   int rhs_mode;          // 1: prescribed displacements present, norms use f - K_fc u_c
   // exact local solve (float64 form): every set's band Cholesky factor of its
-  // region's k^Inner, BAND_CH-column chunks staged through dynamic LDS; null:
-  // preconditioned-CG sweeps
+  // region's k^Inner, by columns and by rows, BAND_CH-column chunks staged
+  // through dynamic LDS; null: preconditioned-CG sweeps
   const double* band;
-  size_t band_stride;    // doubles per set
+  size_t band_stride;    // doubles per set (both copies)
   int band_bs;           // doubles per factor column (diagonal + lower band)
 };
 
 // Exact local solves: columns per LDS chunk of the band factor, and the
 // factor's shape for a relaxation region of at most R x R nodes (R = E + 2w):
-// n = 2 R^2 DOFs, lower bandwidth 2R + 1, so 2R + 2 doubles a column.
-constexpr int BAND_CH = 32;
+// n = 2 R^2 DOFs, lower bandwidth 2R + 1, so 2R + 2 doubles a column.  A set
+// keeps the factor twice: column j of L (the forward solve's order), then row
+// j of L in descending j (the backward solve's order), each BS doubles.
+constexpr int BAND_CH = 64;
 __host__ __device__ constexpr int band_bs(int R) { return 2 * R + 2; }
-__host__ __device__ constexpr size_t band_set_doubles(int R) { return (size_t)2 * R * R * band_bs(R); }
+__host__ __device__ constexpr size_t band_copy_doubles(int R) { return (size_t)2 * R * R * band_bs(R); }
+__host__ __device__ constexpr size_t band_set_doubles(int R) { return 2 * band_copy_doubles(R); }
+// Two chunk buffers, padded by 128 doubles: a column step reads 128 entries
+// past its column's start from its last lane.
 __host__ __device__ constexpr size_t band_chunk_bytes(int R) {
-  return (size_t)2 * BAND_CH * band_bs(R) * sizeof(double);
+  return ((size_t)2 * BAND_CH * band_bs(R) + 128) * sizeof(double);
 }
 
 struct CoarseArgs {

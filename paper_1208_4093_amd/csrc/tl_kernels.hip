@@ -20,6 +20,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace tl {
 
@@ -70,6 +71,12 @@ __device__ __forceinline__ float dpp_move(float v) {
 __device__ __forceinline__ double lane63(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// Lane l's value, l uniform across the wave.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 __device__ __forceinline__ float lane63(float v) {
@@ -256,7 +263,9 @@ __device__ double band_entry(const Geo& g, const float* __restrict__ ea,
 // One workgroup per set: band Cholesky of its region's k^Inner, right-looking,
 // with the b + 1 columns still being updated in an LDS ring (dynamic LDS of
 // (b_max + 1) BS doubles); each column leaves the ring final and the next
-// enters assembled.
+// enters assembled.  A retiring column j is written to the column copy, and
+// its entries L[j+d][j] to the row copy as entry d of row j + d; row j's
+// entries before column 0 or past the band are zeros.
 __global__ __launch_bounds__(256) void k_band_factor(Geo g, int ov, const float* __restrict__ ea,
                                                      const uint8_t* __restrict__ mask,
                                                      double* __restrict__ band) {
@@ -266,6 +275,7 @@ __global__ __launch_bounds__(256) void k_band_factor(Geo g, int ov, const float*
   const int R = g.E + 2 * ov, BS = band_bs(R);
   const int n = br.n, b = br.b, nr = b + 1;
   double* out = band + (size_t)s * band_set_doubles(R);
+  double* rows = out + band_copy_doubles(R);   // row r at (n - 1 - r) BS
   for (int e = t; e < nr * BS; e += 256) {
     const int col = e / BS, d = e % BS;
     ring[e] = d <= b ? band_entry(g, ea, mask, br, col, d) : 0.0;
@@ -285,7 +295,10 @@ __global__ __launch_bounds__(256) void k_band_factor(Geo g, int ov, const float*
     __syncthreads();
     // retire column j; column j + b + 1 takes its slot
     for (int d = t; d < BS; d += 256) {
-      out[(size_t)j * BS + d] = d == 0 ? 1.0 / ljj : (d <= b ? cj[d] : 0.0);
+      const double lv = d == 0 ? 1.0 / ljj : (d <= b ? cj[d] : 0.0);
+      out[(size_t)j * BS + d] = lv;
+      if (d <= b && j + d < n) rows[(size_t)(n - 1 - j - d) * BS + d] = lv;
+      if (d > min(j, b)) rows[(size_t)(n - 1 - j) * BS + d] = 0.0;
       cj[d] = d <= b ? band_entry(g, ea, mask, br, j + nr, d) : 0.0;
     }
     __syncthreads();
@@ -562,14 +575,19 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
   constexpr bool kTwoBarrier = sizeof(T) == 4 && E <= 32;
   T2 x[NPT];
   bool exact = false;
-  if constexpr (sizeof(T) == 8) {
+  if constexpr (sizeof(T) == 8 && E <= 32) {   // the float64 form with sets up to 32 x 32
     if (A.band) {
       // Exact local solve (section 2.2 end): k^Inner delta = r on the
-      // region with the set's band factor.  The residual goes to the node
-      // buffer in DOF order; wave 0 runs the two triangular solves column by
-      // column while the other waves stage the next chunk of factor columns
-      // into LDS.  Within wave 0 each column's LDS updates are seen by the
-      // next column's reads (one wave's LDS operations complete in order).
+      // region with the set's band factor, L y = r, then L^T delta = y.
+      // Both are one kind of pass: step j takes the final v[j] (times the
+      // stored 1/L_jj) and subtracts its multiples from v[j+1 .. j+b], with
+      // the factor's columns (forward) or its rows in descending order
+      // (backward, positions mirrored).  The residual goes to the node buffer
+      // in DOF order.  Wave 0 runs the steps with v in registers: positions
+      // 64k .. 64k + 191 of the current block k, position p in lane p % 64,
+      // and the next pivot read from its lane before the step's updates, so
+      // that one multiply-add per step depends on the last.  The other waves
+      // stage the next BAND_CH factor columns into LDS meanwhile.
       exact = true;
       extern __shared__ double band_lds[];
       constexpr int BS = band_bs(R);
@@ -590,62 +608,104 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         }
       }
       const int nch = (n + BAND_CH - 1) / BAND_CH;
-      auto load_chunk = [&](const int c, double* buf, const int t0, const int nth) {
-        const int j0 = c * BAND_CH, cols = min(BAND_CH, n - j0);
-        const double* src = Lg + (size_t)j0 * BS;
-        for (int e = t0; e < cols * BS; e += nth) buf[e] = src[e];
-      };
       const int wave = t >> 6, lane = t & 63;
-      const int l1 = lane + 1, l2 = lane + 65;
       double* buf0 = band_lds;
       double* buf1 = band_lds + BAND_CH * BS;
-      // forward: L y = r
-      load_chunk(0, buf0, t, NT);
-      __syncthreads();
-      for (int c = 0; c < nch; ++c) {
-        const double* cur = (c & 1) ? buf1 : buf0;
-        if (wave != 0) {
-          if (c + 1 < nch) load_chunk(c + 1, (c & 1) ? buf0 : buf1, t - 64, NT - 64);
-        } else {
-          const int j0 = c * BAND_CH, j1 = min(n, j0 + BAND_CH);
-          for (int j = j0; j < j1; ++j) {
-            const double* col = cur + (j - j0) * BS;
-            const double yj = v[j] * col[0];
-            const double c1 = l1 <= b ? col[l1] : 0.0;
-            const double c2 = l2 <= b ? col[l2] : 0.0;
-            __builtin_amdgcn_wave_barrier();   // every lane has read v[j]
-            if (lane == 0) v[j] = yj;
-            if (l1 <= b && j + l1 < n) v[j + l1] -= c1 * yj;
-            if (l2 <= b && j + l2 < n) v[j + l2] -= c2 * yj;
-            __builtin_amdgcn_wave_barrier();   // the next column reads what this one wrote
-          }
+      // a chunk goes through registers: every load is issued before the
+      // first LDS write waits for its data
+      auto load_chunk = [&](auto nth_c, const double* Lc, const int c, double* buf, const int t0) {
+        constexpr int nth = decltype(nth_c)::value;
+        const int cnt = min(BAND_CH, n - c * BAND_CH) * (BS / 2);
+        const double2* src = reinterpret_cast<const double2*>(Lc + (size_t)c * BAND_CH * BS);
+        double2* dst = reinterpret_cast<double2*>(buf);
+        for (int e0 = t0; e0 < cnt; e0 += 4 * nth) {
+          const bool g1 = e0 + nth < cnt, g2 = e0 + 2 * nth < cnt, g3 = e0 + 3 * nth < cnt;
+          const double2 a = src[e0];
+          const double2 bb = g1 ? src[e0 + nth] : a;
+          const double2 cc = g2 ? src[e0 + 2 * nth] : a;
+          const double2 dd = g3 ? src[e0 + 3 * nth] : a;
+          dst[e0] = a;
+          if (g1) dst[e0 + nth] = bb;
+          if (g2) dst[e0 + 2 * nth] = cc;
+          if (g3) dst[e0 + 3 * nth] = dd;
         }
-        __syncthreads();
-      }
-      // backward: L^T x = y
-      load_chunk(nch - 1, buf0, t, NT);
-      __syncthreads();
-      for (int cc = 0; cc < nch; ++cc) {
-        const int c = nch - 1 - cc;
-        const double* cur = (cc & 1) ? buf1 : buf0;
-        if (wave != 0) {
-          if (c > 0) load_chunk(c - 1, (cc & 1) ? buf0 : buf1, t - 64, NT - 64);
-        } else {
-          const int j0 = c * BAND_CH, j1 = min(n, j0 + BAND_CH);
-          for (int j = j1 - 1; j >= j0; --j) {
-            const double* col = cur + (j - j0) * BS;
-            double sum = 0.0;
-            if (l1 <= b && j + l1 < n) sum += col[l1] * v[j + l1];
-            if (l2 <= b && j + l2 < n) sum += col[l2] * v[j + l2];
-            sum = wave_sum(sum);
-            const double xj = (v[j] - sum) * col[0];
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) v[j] = xj;
-            __builtin_amdgcn_wave_barrier();
-          }
+      };
+      using AllThreads = std::integral_constant<int, NT>;
+      using Loaders = std::integral_constant<int, NT - 64>;
+      auto pass = [&](const double* Lc, const bool mirror) {
+        auto at = [&](const int p) { return mirror ? n - 1 - p : p; };
+        load_chunk(AllThreads{}, Lc, 0, buf0, t);
+        __syncthreads();   // chunk 0, and v complete
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0, piv = 0.0, yprev = 0.0, lprev = 0.0;
+        if (wave == 0) {
+          w0 = lane < n ? v[at(lane)] : 0.0;
+          w1 = lane + 64 < n ? v[at(lane + 64)] : 0.0;
+          w2 = lane + 128 < n ? v[at(lane + 128)] : 0.0;
+          piv = lane_value(w0, 0);
         }
-        __syncthreads();
-      }
+        for (int c = 0; c < nch; ++c) {
+          const double* cur = (c & 1) ? buf1 : buf0;
+          if (wave != 0) {
+            if (c + 1 < nch) load_chunk(Loaders{}, Lc, c + 1, (c & 1) ? buf0 : buf1, t - 64);
+          } else {
+            const int jend = min(BAND_CH, n - c * BAND_CH);
+            // Step jj needs entries lane - jj, lane + 64 - jj and lane + 128 - jj
+            // of column jj: one per-lane address, advanced by BS - 1 doubles a
+            // step, serves all three (the buffers are padded so that reads
+            // of entries past the band stay in LDS; their lanes do not use
+            // them).  The next step's reads are issued before this step's
+            // arithmetic, and the block's last step, whose next pivot is in
+            // the window's second register, is peeled.
+            const double* pl = cur + lane;
+            int dl = lane;   // lane - jj
+            const int b1 = b - 64, b2 = b - 128;
+            double c0 = cur[0], c1 = cur[1], l0 = pl[0], l1 = pl[64], l2 = pl[128];
+            auto step = [&](const int jj, auto last_c) {
+              constexpr bool last = decltype(last_c)::value;
+              double nc0 = 0.0, nc1 = 0.0, nl0 = 0.0, nl1 = 0.0, nl2 = 0.0;
+              if constexpr (!last) {
+                const double* ncol = cur + (jj + 1) * BS;
+                const double* np = pl + (BS - 1);
+                nc0 = ncol[0];
+                nc1 = ncol[1];
+                nl0 = np[0];
+                nl1 = np[64];
+                nl2 = np[128];
+              }
+              __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
+              // piv is v[j] before step j - 1 subtracted its multiple: y_j =
+              // (piv - L[j][j-1] y_{j-1}) / L_jj, one multiply-add after y_{j-1}
+              const double yj = fma(-(lprev * c0), yprev, piv * c0);
+              piv = lane_value(last ? w1 : w0, (jj + 1) & 63);
+              lprev = c1;
+              if (dl >= 1 && dl <= b) w0 = fma(-l0, yj, w0);
+              if (dl == 0) w0 = yj;
+              if (dl <= b1) w1 = fma(-l1, yj, w1);
+              if (dl <= b2) w2 = fma(-l2, yj, w2);
+              yprev = yj;
+              c0 = nc0;
+              c1 = nc1;
+              l0 = nl0;
+              l1 = nl1;
+              l2 = nl2;
+              pl += BS - 1;
+              --dl;
+            };
+            const int jfull = min(jend, BAND_CH - 1);
+            for (int jj = 0; jj < jfull; ++jj) step(jj, std::false_type{});
+            if (jend == BAND_CH) step(BAND_CH - 1, std::true_type{});
+            // positions 64c .. 64c + 63 are final: store them, move the window
+            if (c * 64 + lane < n) v[at(c * 64 + lane)] = w0;
+            w0 = w1;
+            w1 = w2;
+            w2 = (c + 3) * 64 + lane < n ? v[at((c + 3) * 64 + lane)] : 0.0;
+          }
+          __syncthreads();
+        }
+      };
+      static_assert(BAND_CH == 64, "a chunk is one block of the register window");
+      pass(Lg, false);
+      pass(Lg + A.band_stride / 2, true);
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         const int nn = t + k * NT, li = nn % R, lj = nn / R;

@@ -10,7 +10,7 @@ same well-conditioned systems:
 
 * one outer iteration: increment, upper-level blocks and force against the
   model, 1e-10 relative (2-norm per lattice); coefficients that solve the
-  model's upper-level system and the update they give, 1e-8 and 1e-9;
+  model's upper-level system to 1e-8, and the update u_c + U a they give to 1e-9;
 * fifteen outer iterations: the per-iteration max(R1, R2) history against the
   model's, within 5e-8 of the first entry;
 * solves to rtol 1e-10 against the oracle's direct solve, 1e-8 relative;
@@ -46,7 +46,7 @@ def make_lattice(inst, E):
 def band_bytes(nx, ny, E, ov):
     R = E + 2 * ov
     M = -(-nx // E) * -(-ny // E)
-    return M * 2 * R * R * (2 * R + 2) * 8
+    return 2 * M * 2 * R * R * (2 * R + 2) * 8   # by columns and by rows
 
 
 def ov_arg(ov):
@@ -93,7 +93,9 @@ def test_one_iteration_exact_matches_method_model(nx, ny, E, ea, seed, ov):
     # applies them (Eq. 3, 8)
     a_g = tr["coef"].cpu().numpy().reshape(-1)
     assert np.linalg.norm(step.Kc @ a_g - step.P) <= 1e-8 * np.linalg.norm(step.P)
-    assert rel(u.cpu().numpy().reshape(-1), step.u_new) <= 1e-9
+    # (the coefficients themselves are fixed only to K_c's conditioning times
+    # the upper-level residual, so the update is checked with the library's)
+    assert rel(u.cpu().numpy().reshape(-1), S.u_c + step.U @ a_g) <= 1e-9
 
 
 @pytest.mark.parametrize("nx,ny,E,ov", [(60, 45, 16, 2), (80, 70, 32, 1)])
