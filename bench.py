@@ -65,7 +65,7 @@ SINGLE = {
     # the FETCH_SIZE / WRITE_SIZE counter runs (FETCH x 2.0, WRITE x 1.0,
     # calibrated on copy kernels); None when the kernel has changed since the
     # counters were taken.
-    "c2": dict(n=1024, E=32, ea="unit", rtol=1e-8, headline="fp64", traffic_bytes=None,
+    "c2": dict(n=1024, E=32, ea="unit", rtol=1e-8, headline="fp64", traffic_bytes=130.97e6,
                desc="triangle lattice 1024x1024 nodes (2,097,152 DOF), EA=1, L=1, left edge "
                     "clamped, loads N(0,1) seed 0, sets 32x32 nodes, stop at rel. residual 1e-8"),
     "c3": dict(n=16384, E=64, ea="lognormal", rtol=1e-10, headline="mixed", traffic_bytes=None,
@@ -76,7 +76,7 @@ SINGLE = {
 # HBM bytes per launch of the batched workload's dominant tile kernel
 # (k_tile_batch<float, 32, 512, 2>) relative to its algorithmic bytes, from the
 # FETCH_SIZE / WRITE_SIZE counter runs; None when the kernel has changed since.
-C4_TRAFFIC_RATIO = None
+C4_TRAFFIC_RATIO = 1.545
 
 
 # Algorithmic HBM bytes of one tile-kernel launch per lattice node: read u

@@ -80,8 +80,8 @@ struct Job {
 // and in any batch.  The fused kernel hands out its workgroup indices in the
 // order the workgroups start (see k_coarse_batch), so the launch may exceed
 // the device's co-resident capacity when every lattice's own workgroups fit
-// one XCD's share of it; otherwise all of the launch's workgroups must fit
-// at once.  The plan picks an LDS size class (64 KB: two workgroups per CU
+// one XCD's share of it (not under TL_COARSE_BATCH_WG, for tool runs);
+// otherwise all of the launch's workgroups must fit at once.  The plan picks an LDS size class (64 KB: two workgroups per CU
 // beside the static arrays; else 152 KB: one) that every lattice's unstaged
 // slice fits and at which one of those two conditions holds, and enables LDS
 // staging per lattice where it still fits the class.  Returns false when no
@@ -106,7 +106,7 @@ bool plan_coarse(const std::vector<const Geo*>& gs, std::vector<int>* nw_out,
     bool ok = true;
     for (int b = 0; b < n && ok; ++b) ok = coarse_lds_bytes(*gs[b], nw[b], 0, 0, shape[b].two_level) <= cap;
     const int fit = coarse_batch_capacity(cap);   // workgroups resident at once
-    if (!ok || !(used <= fit || largest <= fit / kXcdCount)) continue;
+    if (!ok || !(used <= fit || (coarse_batch_oversubscribe() && largest <= fit / kXcdCount))) continue;
     size_t lds = 0;
     for (int b = 0; b < n; ++b) {
       const int vec = shape[b].vec_lds && coarse_lds_bytes(*gs[b], nw[b], 1, 0, shape[b].two_level) <= cap;

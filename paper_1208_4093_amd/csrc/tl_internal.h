@@ -233,6 +233,7 @@ hipError_t launch_blockinv_batch(const BatchEntry* B, const int* set_lat, int ns
 hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, unsigned* ticket, int nwg,
                                int max_lattice_nwg, size_t lds, hipStream_t stream);
 int coarse_batch_capacity(size_t lds);   // co-resident workgroups of the fused upper-level kernel
+bool coarse_batch_oversubscribe();       // false under TL_COARSE_BATCH_WG: launches fit at once
 hipError_t launch_gather_ctrl(const BatchEntry* B, int n, Ctrl* out, hipStream_t stream);
 // Band Cholesky factors of every set's relaxation region (overlap ov) into
 // band (band_set_doubles(E + 2 ov) doubles per set).

@@ -2573,7 +2573,9 @@ hipError_t launch_blockinv_batch(const BatchEntry* B, const int* set_lat, int ns
 // dynamic LDS: the occupancy per CU times the CUs, or at most the value of
 // TL_COARSE_BATCH_WG when set (for runs under tools that can keep part of the
 // device from a kernel, such as hardware counter collection; a lattice's own
-// workgroup count and with it its results do not change).
+// workgroup count and with it its results do not change).  With the cap set,
+// coarse_batch_oversubscribe() is false: every launch's workgroups must then
+// fit the cap at once.
 int coarse_batch_capacity(size_t lds) {
   static bool attr_set = false;
   if (!attr_set) {
@@ -2597,6 +2599,11 @@ int coarse_batch_capacity(size_t lds) {
   const char* v = getenv("TL_COARSE_BATCH_WG");
   if (v && *v && atoi(v) > 0) cap = std::min(cap, atoi(v));
   return cap;
+}
+
+bool coarse_batch_oversubscribe() {
+  const char* v = getenv("TL_COARSE_BATCH_WG");
+  return !(v && *v && atoi(v) > 0);
 }
 
 hipError_t launch_coarse_batch(const BatchEntry* B, const int* wg_lat, unsigned* ticket, int nwg,
