@@ -57,16 +57,20 @@ __device__ __forceinline__ void set_coords(int i, int j, int i0, int j0, int tw,
 // whose value every lane reads.  All 64 lanes must be active (every call
 // site is workgroup-uniform and every block is a whole number of waves).
 // The order of the additions is fixed, so every wave adds the same way.
+//
+// The moves leave lanes outside their row mask undefined (no old value to
+// set up first): those lanes' sums are never read, since every row mask
+// holds row 3 and only lane 63 is.
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double dpp_move(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, ROWS, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, ROWS, 0xF, false));
 }
 __device__ __forceinline__ double lane63(double v) {
   const long long b = __double_as_longlong(v);
@@ -303,6 +307,16 @@ __global__ __launch_bounds__(256) void k_band_factor(Geo g, int ov, const float*
     }
     __syncthreads();
   }
+}
+
+// alpha and beta of the relaxation sweeps from their float64 sums: a float64
+// quotient in the float64 form; in the float32 form, which rounds them to
+// float32 anyway, the fast float32 quotient (reciprocal and product, a few
+// units of 2^-24) of the sums rounded to float32.
+template <typename T>
+__device__ __forceinline__ T sweep_ratio(double num, double den) {
+  if constexpr (sizeof(T) == 4) return __fdividef((float)num, (float)den);
+  else return num / den;
 }
 
 // ---------------------------------------------------------------------------
@@ -772,18 +786,18 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     auto cell = [&](const int k) { const int n = t + k * NT; return (n / R + 1) * W + (n % R + 1); };
     // z = B^-1 r into the buffer; returns this thread's part of r.z
     auto publish_z = [&]() {
-      double part = 0.0;
+      T part = (T)0;   // a thread's nodes summed in the sweep's precision
   #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         const T2 z = precond(k, rr[k]);
         if (act[k]) sp[cell(k)] = z;
-        part += (double)(rr[k].x * z.x + rr[k].y * z.y);
+        part += rr[k].x * z.x + rr[k].y * z.y;
       }
-      return part;
+      return (double)part;
     };
     // p = z + beta p, K p = K z + beta K p; returns this thread's part of p.Kp
     auto next_direction = [&](const T beta) {
-      double part = 0.0;
+      T part = (T)0;
   #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         if (!act[k]) { pp[k] = qq[k] = mk2<T>((T)0, (T)0); continue; }
@@ -792,9 +806,9 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         const T2 w = apply_k(k, c, z);
         pp[k].x = z.x + beta * pp[k].x;  pp[k].y = z.y + beta * pp[k].y;
         qq[k].x = w.x + beta * qq[k].x;  qq[k].y = w.y + beta * qq[k].y;
-        part += (double)(pp[k].x * qq[k].x + pp[k].y * qq[k].y);
+        part += pp[k].x * qq[k].x + pp[k].y * qq[k].y;
       }
-      return part;
+      return (double)part;
     };
   #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -814,7 +828,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     double pq = block_sum<NW>(next_direction((T)0), sred[1]);
     for (int it = 0; it < A.inner_iters; ++it) {
       if (!(pq > 0.0)) break;
-      const T alpha = (T)(rz / pq);
+      const T alpha = sweep_ratio<T>(rz, pq);
   #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         x[k].x += alpha * pp[k].x;  x[k].y += alpha * pp[k].y;
@@ -825,7 +839,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       //  barrier; likewise the slots of each sum before the other's barrier)
       const double rzn = block_sum<NW>(publish_z(), sred[0]);
       if (!(rzn > rz_stop)) break;
-      const T beta = rz > 0.0 ? (T)(rzn / rz) : (T)0;
+      const T beta = rz > 0.0 ? sweep_ratio<T>(rzn, rz) : (T)0;
       rz = rzn;
       pq = block_sum<NW>(next_direction(beta), sred[1]);
     }
@@ -843,16 +857,16 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       const T Dxy = (T)(0.5 * kS3) * (kb - kc);
       return mk2<T>(idet[k] * (Dyy * rv.x - Dxy * rv.y), idet[k] * (Dxx * rv.y - Dxy * rv.x));
     };
-    double rz_part = 0.0;
+    T rz_part = (T)0;   // a thread's nodes summed in the sweep's precision
   #pragma unroll
     for (int k = 0; k < NPT; ++k) {
       x[k] = mk2<T>((T)0, (T)0);
       const double2 rk = kResidLds ? (act[k] ? sres[t + k * NT] : make_double2(0.0, 0.0)) : r[k];
       rr[k] = mk2<T>((T)(rk.x * scl), (T)(rk.y * scl));
       pp[k] = precond(k, rr[k]);
-      rz_part += (double)(rr[k].x * pp[k].x + rr[k].y * pp[k].y);
+      rz_part += rr[k].x * pp[k].x + rr[k].y * pp[k].y;
     }
-    double rz = block_sum<NW>(rz_part, sred[0]);
+    double rz = block_sum<NW>((double)rz_part, sred[0]);
     // The sweeps end early, uniformly across the workgroup, when the PCG has
     // nothing left to gain: p.Kp <= 0, or r.z has fallen below 2^-60 of its
     // start in float32 (2^-120 in float64), far past the precision's attainable
@@ -868,7 +882,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         sp[(n / R + 1) * W + (n % R + 1)] = pp[k];
       }
       __syncthreads();
-      double pq_part = 0.0;
+      T pq_part = (T)0;
   #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         if (!act[k]) { qq[k] = mk2<T>((T)0, (T)0); continue; }
@@ -898,21 +912,21 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         pb = sp[c + W - 1]; s = (T)kq[2] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
         pb = sp[c - W + 1]; s = (T)kq[5] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
         qq[k] = mk2<T>(qx, qy);
-        pq_part += (double)(pa.x * qx + pa.y * qy);
+        pq_part += pa.x * qx + pa.y * qy;
       }
-      const double pq = block_sum<NW>(pq_part, sred[1]);
+      const double pq = block_sum<NW>((double)pq_part, sred[1]);
       if (!(pq > 0.0)) break;
-      const T alpha = (T)(rz / pq);
-      double rzn_part = 0.0;
+      const T alpha = sweep_ratio<T>(rz, pq);
+      T rzn_part = (T)0;
   #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         x[k].x += alpha * pp[k].x;  x[k].y += alpha * pp[k].y;
         rr[k].x -= alpha * qq[k].x; rr[k].y -= alpha * qq[k].y;
         qq[k] = precond(k, rr[k]);
-        rzn_part += (double)(rr[k].x * qq[k].x + rr[k].y * qq[k].y);
+        rzn_part += rr[k].x * qq[k].x + rr[k].y * qq[k].y;
       }
-      const double rzn = block_sum<NW>(rzn_part, sred[it & 1 ? 0 : 2]);
-      const T beta = rz > 0.0 ? (T)(rzn / rz) : (T)0;
+      const double rzn = block_sum<NW>((double)rzn_part, sred[it & 1 ? 0 : 2]);
+      const T beta = rz > 0.0 ? sweep_ratio<T>(rzn, rz) : (T)0;
       rz = rzn;
   #pragma unroll
       for (int k = 0; k < NPT; ++k) {
