@@ -70,7 +70,7 @@ __device__ __forceinline__ double dpp_move(double v) {
 }
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, ROWS, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, ROWS, 0xF, true));
 }
 __device__ __forceinline__ double lane63(double v) {
   const long long b = __double_as_longlong(v);
@@ -166,6 +166,20 @@ __device__ __forceinline__ T block_sum(T v, double* slot) {
 #pragma unroll
   for (int w = 0; w < NW; ++w) s += slot[w];
   return (T)s;
+}
+
+// Workgroup sum as a float64: the wave sums in the partials' own precision
+// (float32 in the float32 sweeps, where DPP moves fold into the adds), the
+// waves' totals in float64.  Same slot rules as block_sum.
+template <int NW, typename T>
+__device__ __forceinline__ double block_sum_wide(T v, double* slot) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = (double)v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += slot[w];
+  return s;
 }
 
 // Workgroup sum of two values with one barrier; `slot` holds 2 entries per
@@ -311,11 +325,11 @@ __global__ __launch_bounds__(256) void k_band_factor(Geo g, int ov, const float*
 
 // alpha and beta of the relaxation sweeps from their float64 sums: a float64
 // quotient in the float64 form; in the float32 form, which rounds them to
-// float32 anyway, the fast float32 quotient (reciprocal and product, a few
-// units of 2^-24) of the sums rounded to float32.
+// float32 anyway, the sums rounded to float32 and the numerator times the
+// hardware reciprocal of the denominator (within a few units of 2^-24).
 template <typename T>
 __device__ __forceinline__ T sweep_ratio(double num, double den) {
-  if constexpr (sizeof(T) == 4) return __fdividef((float)num, (float)den);
+  if constexpr (sizeof(T) == 4) return (float)num * __builtin_amdgcn_rcpf((float)den);
   else return num / den;
 }
 
@@ -793,7 +807,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         if (act[k]) sp[cell(k)] = z;
         part += rr[k].x * z.x + rr[k].y * z.y;
       }
-      return (double)part;
+      return part;
     };
     // p = z + beta p, K p = K z + beta K p; returns this thread's part of p.Kp
     auto next_direction = [&](const T beta) {
@@ -808,7 +822,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         qq[k].x = w.x + beta * qq[k].x;  qq[k].y = w.y + beta * qq[k].y;
         part += pp[k].x * qq[k].x + pp[k].y * qq[k].y;
       }
-      return (double)part;
+      return part;
     };
   #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -817,7 +831,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       const double2 rk = kResidLds ? (act[k] ? sres[t + k * NT] : make_double2(0.0, 0.0)) : r[k];
       rr[k] = mk2<T>((T)(rk.x * scl), (T)(rk.y * scl));
     }
-    double rz = block_sum<NW>(publish_z(), sred[0]);
+    double rz = block_sum_wide<NW>(publish_z(), sred[0]);
     // The sweeps end early, uniformly across the workgroup, when the PCG has
     // nothing left to gain: p.Kp <= 0, or r.z has fallen below 2^-60 of its
     // start in float32 (2^-120 in float64), far past the precision's attainable
@@ -825,7 +839,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
     // underflowing values, and in float32 they can diverge after a thousand or
     // so further sweeps.  The default sweep counts never reach the threshold.
     const double rz_stop = rz * (sizeof(T) == 4 ? 0x1p-60 : 0x1p-120);
-    double pq = block_sum<NW>(next_direction((T)0), sred[1]);
+    double pq = block_sum_wide<NW>(next_direction((T)0), sred[1]);
     for (int it = 0; it < A.inner_iters; ++it) {
       if (!(pq > 0.0)) break;
       const T alpha = sweep_ratio<T>(rz, pq);
@@ -837,11 +851,11 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       if (it + 1 == A.inner_iters) break;
       // (the buffer is free: every read of it as z came before the last p.Kp
       //  barrier; likewise the slots of each sum before the other's barrier)
-      const double rzn = block_sum<NW>(publish_z(), sred[0]);
+      const double rzn = block_sum_wide<NW>(publish_z(), sred[0]);
       if (!(rzn > rz_stop)) break;
       const T beta = rz > 0.0 ? sweep_ratio<T>(rzn, rz) : (T)0;
       rz = rzn;
-      pq = block_sum<NW>(next_direction(beta), sred[1]);
+      pq = block_sum_wide<NW>(next_direction(beta), sred[1]);
     }
 
   } else {
@@ -866,7 +880,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       pp[k] = precond(k, rr[k]);
       rz_part += rr[k].x * pp[k].x + rr[k].y * pp[k].y;
     }
-    double rz = block_sum<NW>((double)rz_part, sred[0]);
+    double rz = block_sum_wide<NW>(rz_part, sred[0]);
     // The sweeps end early, uniformly across the workgroup, when the PCG has
     // nothing left to gain: p.Kp <= 0, or r.z has fallen below 2^-60 of its
     // start in float32 (2^-120 in float64), far past the precision's attainable
@@ -914,7 +928,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         qq[k] = mk2<T>(qx, qy);
         pq_part += pa.x * qx + pa.y * qy;
       }
-      const double pq = block_sum<NW>((double)pq_part, sred[1]);
+      const double pq = block_sum_wide<NW>(pq_part, sred[1]);
       if (!(pq > 0.0)) break;
       const T alpha = sweep_ratio<T>(rz, pq);
       T rzn_part = (T)0;
@@ -925,7 +939,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         qq[k] = precond(k, rr[k]);
         rzn_part += rr[k].x * qq[k].x + rr[k].y * qq[k].y;
       }
-      const double rzn = block_sum<NW>((double)rzn_part, sred[it & 1 ? 0 : 2]);
+      const double rzn = block_sum_wide<NW>(rzn_part, sred[it & 1 ? 0 : 2]);
       const T beta = rz > 0.0 ? sweep_ratio<T>(rzn, rz) : (T)0;
       rz = rzn;
   #pragma unroll
