@@ -323,6 +323,38 @@ __global__ __launch_bounds__(256) void k_band_factor(Geo g, int ov, const float*
   }
 }
 
+// The six rods' neighbour terms of k^Inner times the node buffer at cell c
+// (row pitch W), subtracted from (qx, qy).  In float32 opposite rods, which
+// pull along the same unit vector, have their two axial terms summed before
+// they are resolved into x and y: rods north and south along n1 = (1/2,
+// sqrt3/2), north-west and south-east along n2 = (-1/2, sqrt3/2), with
+// 2 n.p = +-p.x + sqrt3 p.y; east and west rods act on x alone.
+template <typename T, int W, typename T2>
+__device__ __forceinline__ void rod_neighbours(const T2* sp, const int c, const float* kq, T& qx,
+                                               T& qy) {
+  if constexpr (sizeof(T) == 8) {
+    // (float64: one rod at a time, which holds fewer registers; summing the
+    //  pairs first made the 32 x 32 tile spill 92 bytes per lane, not 36)
+    T2 pb;
+    T s;
+    pb = sp[c + 1];     s = (T)kq[0] * pb.x;                                qx -= s;
+    pb = sp[c - 1];     s = (T)kq[3] * pb.x;                                qx -= s;
+    pb = sp[c + W];     s = (T)kq[1] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
+    pb = sp[c - W];     s = (T)kq[4] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
+    pb = sp[c + W - 1]; s = (T)kq[2] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+    pb = sp[c - W + 1]; s = (T)kq[5] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+    return;
+  }
+  constexpr T r3 = (T)(2.0 * kS3);
+  const T2 pe = sp[c + 1], pw = sp[c - 1], pn = sp[c + W], ps = sp[c - W];
+  const T2 pnw = sp[c + W - 1], pse = sp[c - W + 1];
+  qx -= (T)kq[0] * pe.x + (T)kq[3] * pw.x;
+  const T s1 = (T)kq[1] * (pn.x + r3 * pn.y) + (T)kq[4] * (ps.x + r3 * ps.y);     // 2 k n1.p
+  const T s2 = (T)kq[2] * (r3 * pnw.y - pnw.x) + (T)kq[5] * (r3 * pse.y - pse.x);  // 2 k n2.p
+  qx += (T)0.25 * (s2 - s1);
+  qy -= (T)(0.5 * kS3) * (s1 + s2);
+}
+
 // alpha and beta of the relaxation sweeps from their float64 sums: a float64
 // quotient in the float64 form; in the float32 form, which rounds them to
 // float32 anyway, the sums rounded to float32 and the numerator times the
@@ -788,13 +820,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
       const T Dxy = (T)(0.5 * kS3) * (kb - kc);
       T qx = Dxx * za.x + Dxy * za.y;
       T qy = Dxy * za.x + Dyy * za.y;
-      T2 pb; T s;
-      pb = sp[c + 1];     s = (T)kq[0] * pb.x;                                qx -= s;
-      pb = sp[c - 1];     s = (T)kq[3] * pb.x;                                qx -= s;
-      pb = sp[c + W];     s = (T)kq[1] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
-      pb = sp[c - W];     s = (T)kq[4] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
-      pb = sp[c + W - 1]; s = (T)kq[2] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
-      pb = sp[c - W + 1]; s = (T)kq[5] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+      rod_neighbours<T, W>(sp, c, kq, qx, qy);
       return mk2<T>(qx, qy);
     };
     auto cell = [&](const int k) { const int n = t + k * NT; return (n / R + 1) * W + (n % R + 1); };
@@ -918,13 +944,7 @@ __device__ __forceinline__ void tile_body(const Geo& g, const float* __restrict_
         const T Dxy = (T)(0.5 * kS3) * (kb - kc);
         T qx = Dxx * pa.x + Dxy * pa.y;
         T qy = Dxy * pa.x + Dyy * pa.y;
-        T2 pb; T s;
-        pb = sp[c + 1];     s = (T)kq[0] * pb.x;                                qx -= s;
-        pb = sp[c - 1];     s = (T)kq[3] * pb.x;                                qx -= s;
-        pb = sp[c + W];     s = (T)kq[1] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
-        pb = sp[c - W];     s = (T)kq[4] * ((T)0.5 * pb.x + (T)kS3 * pb.y);   qx -= (T)0.5 * s; qy -= (T)kS3 * s;
-        pb = sp[c + W - 1]; s = (T)kq[2] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
-        pb = sp[c - W + 1]; s = (T)kq[5] * ((T)-0.5 * pb.x + (T)kS3 * pb.y);  qx += (T)0.5 * s; qy -= (T)kS3 * s;
+        rod_neighbours<T, W>(sp, c, kq, qx, qy);
         qq[k] = mk2<T>(qx, qy);
         pq_part += pa.x * qx + pa.y * qy;
       }
