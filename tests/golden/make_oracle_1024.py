@@ -1,0 +1,59 @@
+"""Write the oracle's solution of the 1024 x 1024 workload lattice at sampled
+DOFs (test infrastructure: calls only the oracle and the input generator).
+
+    python tests/golden/make_oracle_1024.py tests/golden/oracle_u_1024_sample.json
+
+The lattice is the benchmark's 1024 x 1024 instance (EA 1, nodes i = 0 clamped,
+loads N(0, 1) with seed 0).  The oracle's block-Jacobi PCG runs until its
+recomputed relative 2-norm residual is 1e-13; the file holds that residual,
+max(R1, R2) of Eq. 19, the 2-norm of the whole solution, and the solution at
+4,000 DOFs drawn without replacement (seed 12345) among the free ones.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", ".."))
+
+from oracle.solve import rel_residuals, solve_pcg, system_of  # noqa: E402
+from workloads import make_instance  # noqa: E402
+
+N = 1024
+SAMPLES = 4000
+SAMPLE_SEED = 12345
+RTOL = 1e-13
+
+
+def main():
+    out = sys.argv[1]
+    inst = make_instance(N, N, seed=0)
+    S = system_of(inst)
+    t0 = time.perf_counter()
+    hist = []
+    u = solve_pcg(S, rtol=RTOL, history=hist)
+    seconds = time.perf_counter() - t0
+    R1, R2 = rel_residuals(S, u)
+    b = S.rhs
+    res2 = float(np.linalg.norm(b - S.Kff @ u[S.free]) / np.linalg.norm(b))
+    free = np.flatnonzero(S.free)
+    idx = np.sort(np.random.default_rng(SAMPLE_SEED).choice(free, SAMPLES, replace=False))
+    rec = {
+        "lattice": [N, N], "seed": 0, "ea": "unit", "clamp": "left",
+        "solver": "oracle.solve.solve_pcg (block-Jacobi PCG on K_ff)",
+        "rtol": RTOL, "iterations": len(hist), "seconds": seconds,
+        "rel_residual_2norm": res2, "R1": float(R1), "R2": float(R2),
+        "u_norm2": float(np.linalg.norm(u)),
+        "sample_seed": SAMPLE_SEED,
+        "dof": [int(i) for i in idx],
+        "u": [float(v) for v in u[idx]],
+    }
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=0)
+    print(f"{len(hist)} iterations in {seconds:.0f} s, residual {res2:.3e}, R = {max(R1, R2):.3e}")
+
+
+if __name__ == "__main__":
+    main()
