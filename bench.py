@@ -68,7 +68,7 @@ SINGLE = {
     "c2": dict(n=1024, E=32, ea="unit", rtol=1e-8, headline="fp64", traffic_bytes=130.97e6,
                desc="triangle lattice 1024x1024 nodes (2,097,152 DOF), EA=1, L=1, left edge "
                     "clamped, loads N(0,1) seed 0, sets 32x32 nodes, stop at rel. residual 1e-8"),
-    "c3": dict(n=16384, E=64, ea="lognormal", rtol=1e-10, headline="mixed", traffic_bytes=None,
+    "c3": dict(n=16384, E=64, ea="lognormal", rtol=1e-10, headline="mixed", traffic_bytes=22.09e9,
                desc="triangle lattice 16384x16384 nodes (536,870,912 DOF), EA lognormal(0,0.5), "
                     "left edge clamped, loads N(0,1) seed 0, sets 64x64 nodes, mixed precision, "
                     "stop at rel. residual 1e-10"),

@@ -307,6 +307,32 @@ def test_full_size_1024_certified(precision):
     assert abs(fu - uKu) <= 1e-6 * abs(fu)
 
 
+@pytest.mark.parametrize("precision", [tl.TL_FP64, tl.TL_MIXED])
+def test_full_size_1024_against_oracle_solution(precision):
+    """The 1024 x 1024 workload against the oracle's own solution of it (block-
+    Jacobi PCG to a recomputed relative residual of 1e-13, written by
+    tests/golden/make_oracle_1024.py) at its 4,000 sampled free DOFs: solved
+    to 1e-10 (the parity tolerance of the method's readings) the relative
+    error over the sample is at most 1e-8; at the benchmark's 1e-8 it is
+    reported and held to 1e-6 (the relative error of CG-type iterates runs at
+    a fraction of the relative residual here, far below kappa(K) times it)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_u_1024_sample.json")
+    ref = json.load(open(path))
+    assert ref["rel_residual_2norm"] <= 1e-13 and ref["lattice"] == [1024, 1024]
+    idx = np.asarray(ref["dof"])
+    want = np.asarray(ref["u"])
+    inst = make_instance(1024, 1024, seed=0)
+    for rtol, bound in ((1e-10, 1e-8), (1e-8, 1e-6)):
+        u, info, _ = gpu_solve(inst, 32, precision, rtol)
+        assert info["status"] == tl.TL_OK
+        got = u.reshape(-1)[idx]
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        print(f"precision {precision} rtol {rtol:g}: sampled relative error {err:.3e}")
+        assert err <= bound, (rtol, err)
+
+
 def test_unsupported_overlap_is_rejected():
     inst = make_instance(40, 30, seed=13)
     lat = make_lattice(inst, 16)
