@@ -319,6 +319,9 @@ def test_full_size_1024_against_oracle_solution(precision):
     import json
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "oracle_u_1024_sample.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/oracle_u_1024_sample.json not written yet "
+                    "(python tests/golden/make_oracle_1024.py tests/golden/oracle_u_1024_sample.json)")
     ref = json.load(open(path))
     assert ref["rel_residual_2norm"] <= 1e-13 and ref["lattice"] == [1024, 1024]
     idx = np.asarray(ref["dof"])
