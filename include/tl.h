@@ -122,10 +122,13 @@ typedef struct {
                                   1: exact (section 2.2 end: each set's region
                                   stiffness k^Inner is factored once, band Cholesky,
                                   on the first such solve of the lattice and
-                                  overlap, kept with the lattice and reused).  Float64
-                                  form only, sets of at most 32 x 32 nodes;
-                                  else TL_E_INVAL.  The factors take about
-                                  64 (E + 2w)^3 bytes per set                      */
+                                  overlap, kept with the lattice and reused; that
+                                  first call, batched or served too, synchronises
+                                  its stream once).  Float64 form only, sets of at
+                                  most 32 x 32 nodes; else TL_E_INVAL.  The factors
+                                  take about 64 (E + 2w)^3 bytes per set, counted
+                                  in tl_lattice_facts.device_bytes; TL_E_NOMEM when
+                                  they do not fit                                  */
 } tl_opts;
 
 typedef struct {
