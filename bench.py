@@ -76,7 +76,7 @@ SINGLE = {
 # HBM bytes per launch of the batched workload's dominant tile kernel
 # (k_tile_batch<float, 32, 512, 2>) relative to its algorithmic bytes, from the
 # FETCH_SIZE / WRITE_SIZE counter runs; None when the kernel has changed since.
-C4_TRAFFIC_RATIO = 1.545
+C4_TRAFFIC_RATIO = 1.683
 
 
 # Algorithmic HBM bytes of one tile-kernel launch per lattice node: read u
