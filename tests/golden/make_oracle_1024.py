@@ -5,9 +5,11 @@ DOFs (test infrastructure: calls only the oracle and the input generator).
 
 The lattice is the benchmark's 1024 x 1024 instance (EA 1, nodes i = 0 clamped,
 loads N(0, 1) with seed 0).  The oracle's block-Jacobi PCG runs until its
-recomputed relative 2-norm residual is 1e-13; the file holds that residual,
-max(R1, R2) of Eq. 19, the 2-norm of the whole solution, and the solution at
-4,000 DOFs drawn without replacement (seed 12345) among the free ones.
+recomputed relative 2-norm residual is 1e-11 (float64 PCG on this system
+cannot reach much below that: the recomputed residual of b - K x stalls near
+eps ||K|| ||x|| / ||b||); the file holds that residual, max(R1, R2) of Eq. 19,
+the 2-norm of the whole solution, and the solution at 4,000 DOFs drawn without
+replacement (seed 12345) among the free ones.
 """
 import json
 import os
@@ -24,7 +26,7 @@ from workloads import make_instance  # noqa: E402
 N = 1024
 SAMPLES = 4000
 SAMPLE_SEED = 12345
-RTOL = 1e-13
+RTOL = 1e-11
 
 
 def main():
@@ -33,11 +35,13 @@ def main():
     S = system_of(inst)
     t0 = time.perf_counter()
     hist = []
-    u = solve_pcg(S, rtol=RTOL, history=hist)
+    u = solve_pcg(S, rtol=RTOL, history=hist, max_seconds=5400.0)
     seconds = time.perf_counter() - t0
     R1, R2 = rel_residuals(S, u)
     b = S.rhs
     res2 = float(np.linalg.norm(b - S.Kff @ u[S.free]) / np.linalg.norm(b))
+    if not res2 <= RTOL:
+        raise SystemExit(f"the oracle's PCG stopped at a relative residual of {res2:.3e} > {RTOL:g}")
     free = np.flatnonzero(S.free)
     idx = np.sort(np.random.default_rng(SAMPLE_SEED).choice(free, SAMPLES, replace=False))
     rec = {

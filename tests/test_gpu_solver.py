@@ -310,7 +310,7 @@ def test_full_size_1024_certified(precision):
 @pytest.mark.parametrize("precision", [tl.TL_FP64, tl.TL_MIXED])
 def test_full_size_1024_against_oracle_solution(precision):
     """The 1024 x 1024 workload against the oracle's own solution of it (block-
-    Jacobi PCG to a recomputed relative residual of 1e-13, written by
+    Jacobi PCG to a recomputed relative residual of 1e-11, written by
     tests/golden/make_oracle_1024.py) at its 4,000 sampled free DOFs: solved
     to 1e-10 (the parity tolerance of the method's readings) the relative
     error over the sample is at most 1e-8; at the benchmark's 1e-8 it is
@@ -323,7 +323,7 @@ def test_full_size_1024_against_oracle_solution(precision):
         pytest.skip("tests/golden/oracle_u_1024_sample.json not written yet "
                     "(python tests/golden/make_oracle_1024.py tests/golden/oracle_u_1024_sample.json)")
     ref = json.load(open(path))
-    assert ref["rel_residual_2norm"] <= 1e-13 and ref["lattice"] == [1024, 1024]
+    assert ref["rel_residual_2norm"] <= 1e-11 and ref["lattice"] == [1024, 1024]
     idx = np.asarray(ref["dof"])
     want = np.asarray(ref["u"])
     inst = make_instance(1024, 1024, seed=0)
