@@ -268,6 +268,23 @@ def common_fields(args, value, ms_per_step, dtype, config):
 
 # ------------------------------------------------------ single lattices
 
+def sampled_error_vs_reference(wl, u):
+    """Relative 2-norm error of the solution u (a device tensor) at the
+    sampled DOFs of the oracle's stored reference solution of this workload
+    (tests/golden/oracle_u_1024_sample.json: the 1024 x 1024 lattice only), or
+    None when there is no reference for it."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                        "oracle_u_1024_sample.json")
+    if wl["n"] != 1024 or wl["ea"] != "unit" or not os.path.exists(path):
+        return None
+    import numpy as np
+    ref = json.load(open(path))
+    idx = np.asarray(ref["dof"])
+    want = np.asarray(ref["u"])
+    got = u.reshape(-1).cpu().numpy()[idx]
+    return float(np.linalg.norm(got - want) / np.linalg.norm(want))
+
+
 def run_single(args, wl, steps=None, warmup=None):
     import torch
     from paper_1208_4093_amd import tl
@@ -322,7 +339,9 @@ def run_single(args, wl, steps=None, warmup=None):
         kern = {"tile": full["tile_ms"], "offdiag": full["offdiag_ms"], "coarse": full["coarse_ms"]}
         per_launch = {k: v / max(full["tile_launches"], 1) for k, v in kern.items()}
         per_launch["tile"] = tile_ms
+        err = sampled_error_vs_reference(wl, u)
         return {
+            "rel_err_vs_oracle_sample": err,
             "value": inst.dof * len(ok) / wall, "ms_per_step": 1000.0 * wall / steps,
             "p50_ms": percentile(lat_ms, 50), "p99_ms": percentile(lat_ms, 99),
             "iters": infos[-1]["iters"], "coarse_iters": infos[-1]["coarse_iters"],
@@ -351,6 +370,7 @@ def run_single(args, wl, steps=None, warmup=None):
                    "local_solve": "exact" if exact else "pcg"},
         "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
         "iters": head["iters"], "coarse_iters": head["coarse_iters"], "rel_res": head["rel_res"],
+        "rel_err_vs_oracle_sample": head["rel_err_vs_oracle_sample"],
         "failed": head["failed"], "kernel_ms_per_launch": head["kernel_ms_per_launch"],
         "kernel_share": head["kernel_share"],
         "coarse_us_per_pcg_iteration": head["coarse_us_per_pcg_iteration"],
@@ -370,7 +390,8 @@ def run_single(args, wl, steps=None, warmup=None):
         other = res[forms[1]]
         out["mixed" if wl["headline"] == "fp64" else "fp64"] = {
             k: other[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "iters", "rel_res",
-                                  "failed", "kernel_ms_per_launch", "tile_gbs")}
+                                  "rel_err_vs_oracle_sample", "failed", "kernel_ms_per_launch",
+                                  "tile_gbs")}
         m, d = (res[tl.TL_MIXED], res[tl.TL_FP64])
         out["mixed_over_fp64"] = m["value"] / d["value"]
     lat.close()
