@@ -75,6 +75,12 @@ typedef enum {
                               scaling; residual, upper level, update in float64 */
 } tl_precision;
 
+typedef enum {
+    TL_LOCAL_PCG = 0,      /* relaxation by preconditioned-CG sweeps (default)    */
+    TL_LOCAL_EXACT = 1     /* exact relaxation with the regions' band Cholesky
+                              factors, built once per lattice and overlap     */
+} tl_local_solve;
+
 typedef struct {
     int32_t nx, ny;            /* nodes per side, each >= 2                      */
     const float* ea;           /* [3][ny][nx]; NULL = every rod EA 1             */
@@ -118,13 +124,14 @@ typedef struct {
                                   nodes on every side, keeping the increment on the
                                   set (section 2.2 end): 1, 2 or 4; -1 = the set
                                   alone; 0 = library default (2)                    */
-    int32_t local_solve;       /* 0: the relaxation by inner_iters PCG sweeps (default);
-                                  1: exact (section 2.2 end: each set's region
-                                  stiffness k^Inner is factored once, band Cholesky,
+    int32_t local_solve;       /* a tl_local_solve.  TL_LOCAL_PCG (0): relaxation by
+                                  inner_iters PCG sweeps (default).  TL_LOCAL_EXACT
+                                  (1): exact (section 2.2 end): each set's region
+                                  stiffness k^Inner is factored once (band Cholesky)
                                   on the first such solve of the lattice and
                                   overlap, kept with the lattice and reused; that
                                   first call, batched or served too, synchronises
-                                  its stream once).  Float64 form only, sets of at
+                                  its stream once.  Float64 form only, sets of at
                                   most 32 x 32 nodes; else TL_E_INVAL.  The factors
                                   take about 64 (E + 2w)^3 bytes per set, counted
                                   in tl_lattice_facts.device_bytes; TL_E_NOMEM when
