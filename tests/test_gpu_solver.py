@@ -217,6 +217,58 @@ def test_overlap_solve_matches_oracle(nx, ny, E, ea, seed, ov, precision):
     assert err <= 1e-8, (err, info)
 
 
+# Every tile kernel the library can launch: set edge 16, 32 or 64 (as a caller
+# or the autotuner picks it), each thread count the launcher takes for it
+# (its default, or TL_TILE_THREADS), relaxation overlap 0, 1, 2 or 4 (section
+# 2.2 end), in both forms, solved against the oracle on a ragged lattice of
+# several sets.
+TILE_LATTICES = {16: (45, 37), 32: (75, 70), 64: (140, 70)}
+TILE_SHAPES = [(16, 256, ov) for ov in (0, 1, 2, 4)] + \
+    [(32, 256, ov) for ov in (0, 1, 2, 4)] + [(32, 512, ov) for ov in (0, 1, 2, 4)] + \
+    [(32, 1024, 0)] + [(64, nt, ov) for nt in (512, 1024) for ov in (0, 1, 2, 4)]
+_tile_refs = {}
+
+
+def _tile_case(E):
+    if E not in _tile_refs:
+        nx, ny = TILE_LATTICES[E]
+        inst = make_instance(nx, ny, seed=100 + E, ea="lognormal")
+        _tile_refs[E] = (inst, solve(system_of(inst)))
+    return _tile_refs[E]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("E,nt,ov", TILE_SHAPES)
+def test_every_tile_instantiation_matches_oracle(E, nt, ov, precision, monkeypatch):
+    monkeypatch.setenv("TL_TILE_THREADS", str(nt))
+    inst, us = _tile_case(E)
+    u, info, _ = gpu_solve(inst, E, precision, 1e-10, overlap=ov if ov > 0 else -1)
+    assert info["status"] == tl.TL_OK
+    assert max(info["rel_res_l1"], info["rel_res_l2"]) <= 1e-10
+    err = np.linalg.norm(u.reshape(-1) - us) / np.linalg.norm(us)
+    assert err <= 1e-8, (err, info)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("ov", [0, 1, 2, 4])
+def test_every_batched_tile_instantiation_matches_oracle(ov, precision):
+    """The fused batch's tile kernels at each overlap, one lattice per set edge
+    in one call, against the same oracle solutions."""
+    cases = [_tile_case(E) for E in (16, 32, 64)]
+    lats = [make_lattice(inst, E) for E, (inst, _) in zip((16, 32, 64), cases)]
+    fs = [dev(inst.f) for inst, _ in cases]
+    us = [torch.zeros_like(f) for f in fs]
+    st, infos = tl.tl_solve_batch(lats, fs, us, precision=precision, rtol=1e-10,
+                                  overlap=ov if ov > 0 else -1)
+    torch.cuda.synchronize()
+    assert st == tl.TL_OK
+    for (inst, ref), u, info in zip(cases, us, infos):
+        assert info["status"] == tl.TL_OK
+        assert max(info["rel_res_l1"], info["rel_res_l2"]) <= 1e-10
+        err = np.linalg.norm(u.cpu().numpy().reshape(-1) - ref) / np.linalg.norm(ref)
+        assert err <= 1e-8, (err, info)
+
+
 def test_energy_decreases_every_iteration():
     inst = make_instance(50, 41, seed=11, ea="lognormal")
     lat = make_lattice(inst, 16)
