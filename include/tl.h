@@ -42,6 +42,27 @@
  * Errors
  *   Every call returns a tl_status; nothing aborts or throws across the ABI.
  *   TL_E_NOCONV still writes the last iterate to u and fills the tl_info.
+ *
+ * Environment (tuning and diagnostics; read at each call, unset = default)
+ *   TL_TUNE_CACHE          file of measured set edges, overlaps and sweeps
+ *                          (tl_tune, below).
+ *   TL_TILE_THREADS        threads of the tile kernel where the set edge
+ *                          allows several: 256/512/1024 for 32 x 32 sets
+ *                          without overlap, 256/512 with it, 512/1024 for
+ *                          64 x 64; other values keep the default.
+ *   TL_COARSE_SETS_PER_WG  sets per upper-level workgroup (default 16).
+ *   TL_COARSE_2LEVEL       0: no aggregate coarse space in the upper-level
+ *                          preconditioner (block Jacobi alone).
+ *   TL_COARSE_NO_LDS       1: upper-level vectors and blocks stay in HBM.
+ *   TL_COARSE_WARM         0: the upper-level PCG starts from zero instead
+ *                          of the previous coefficients.
+ *   TL_COARSE_REF          1: its tolerance is relative to the zero-start
+ *                          residual instead of the initial one.
+ *   TL_COARSE_BATCH_WG     cap on co-resident workgroups of the fused
+ *                          upper-level kernel (for profilers that keep part
+ *                          of the device); results do not change.
+ *   None of these changes the method; each changes only how the work is
+ *   laid out or how far the upper-level PCG iterates.
  */
 #ifndef TL_H
 #define TL_H

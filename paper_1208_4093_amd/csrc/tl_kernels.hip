@@ -2514,9 +2514,10 @@ int grid_for(size_t n, int nt, int cap) {
 // Threads per tile workgroup for each set edge, precision and overlap
 // (measured without overlap: 256 for E = 32; 512 for E = 64 in float32, 1024
 // in float64, where 512 threads spill).  With overlap the region holds
-// (E + 2 OV)^2 nodes: 256 threads for E = 16; for 64, 512 in float32 with
-// overlaps up to 2 (ten nodes per thread in 256 registers; 1.02x faster than
-// 1024 threads at 128) and 1024 otherwise; for 32, 512 (three nodes per
+// (E + 2 OV)^2 nodes: 256 threads for E = 16; for 64, 512 in float32 (ten
+// or eleven nodes per thread in 256 registers; at 4096^2 1.20x faster than
+// 1024 threads at 128 with overlap 2, 1.38x with overlap 4) and 1024 in
+// float64 (1.28x faster than 512 with overlap 2, 1.09x with 4); for 32, 512 (three nodes per
 // thread; in float64 256 or 1024 threads were 1.3x slower; in float32 256
 // threads, two tiles per CU without spills, were 1.02-1.07x faster on single
 // lattices from 1024^2 up but 1.02x slower in fused batches and served
@@ -2529,7 +2530,7 @@ static int tile_threads(int E, bool mixed, int ov) {
   if (E == 16) return 256;
   if (ov > 0) {
     if (E == 32) return env == 256 || env == 512 ? env : 512;
-    return env == 512 || env == 1024 ? env : (mixed && ov <= 2 ? 512 : 1024);
+    return env == 512 || env == 1024 ? env : (mixed ? 512 : 1024);
   }
   if (E == 32) return env == 256 || env == 512 || env == 1024 ? env : 256;
   return env == 512 || env == 1024 ? env : (mixed ? 512 : 1024);
