@@ -169,9 +169,10 @@ class ForceLocalSolver:
     gives the increment of Eq. 17 directly:
         (k^Inner + Delta k) (u^RF - u^old) = (p - K u^old)|_region,
     whose right-hand side is the residual on the region.  Where the isolated
-    region can move rigidly, the minimum-norm solution is taken: with N an
-    orthonormal basis of the region's rigid motions that the isolated
-    stiffness does not resist, the bordered system
+    stiffness is singular, the minimum-norm solution is taken: with N an
+    orthonormal basis of what it does not resist (the region's rigid motions,
+    and for a region one node thick also the motions across the strip), the
+    bordered system
         [[K_iso, N], [N^T, 0]] [x; l] = [r; 0]
     gives K_iso x = r - N N^T r with N^T x = 0.  Factors are computed once and
     reused.  The increment is kept on the set's own DOFs."""
@@ -197,7 +198,7 @@ class ForceLocalSolver:
                 continue
             dk = isolation_correction(K, idx, inside)
             kiso = (K[idx][:, idx] + dk).tocsc()
-            N = self._rigid_null_space(kiso, idx, x, y)
+            N = self._null_space(kiso, idx, x, y)
             self.dk.append(dk)
             self.kiso.append(kiso)
             self.null.append(N)
@@ -207,6 +208,21 @@ class ForceLocalSolver:
                 self.lu.append(spla.splu(A))
             else:
                 self.lu.append(spla.splu(kiso))
+
+    @staticmethod
+    def _null_space(kiso, idx, x, y):
+        """Orthonormal basis of the displacements of the region's free DOFs
+        that kiso does not resist.  A region of at most 256 free DOFs, which
+        includes every region one node thick (a strip of rods along one line
+        resists nothing across it, a mechanism beyond the rigid motions),
+        takes it from kiso's dense eigenvectors; a larger region, at least
+        two nodes thick and so triangulated, can only move rigidly, and the
+        rigid motions are tested."""
+        if idx.size <= 256:
+            scale = abs(kiso).sum(axis=1).max()
+            w, V = np.linalg.eigh(kiso.toarray())
+            return V[:, w <= 1e-10 * scale]
+        return ForceLocalSolver._rigid_null_space(kiso, idx, x, y)
 
     @staticmethod
     def _rigid_null_space(kiso, idx, x, y):

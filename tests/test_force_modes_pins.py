@@ -9,6 +9,10 @@ against facts that do not come from the oracle's own code:
 * for a floating region the increment is the minimum-norm solution: the
   isolated stiffness maps it to the residual minus its rigid-motion part, and
   it is orthogonal to the rigid motions;
+* on every region of a lattice with a ragged set row one node thick and two
+  clamped corners (strips, floating regions, regions pinned at one node) the
+  increment is the dense pseudo-inverse of the loop-built isolated stiffness
+  applied to the residual;
 * modes 10-12 span {d_F, x d_F, y d_F} on each set (Eq. 17-18);
 * with q = 12 the method keeps its invariants (the energy of Eq. 2 never
   rises, Galerkin orthogonality to all twelve modes, convergence to the plain
@@ -136,6 +140,42 @@ def test_floating_region_gives_the_minimum_norm_increment():
         Kd = fs.kiso[I].toarray()
         assert np.linalg.norm(Kd @ x - rhs) <= 1e-10 * np.linalg.norm(rhs)
         assert np.linalg.norm(Q.T @ x) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_every_region_increment_is_the_pseudo_inverse_solution():
+    """Regions one node thick (the ragged top row of 16 x 16 sets on 33 rows,
+    w = 0), regions with no clamped node and with exactly one (two opposite
+    corners clamped): on each, the increment is the minimum-norm solution,
+    the dense pseudo-inverse of the rods inside the region (assembled by the
+    loop above) applied to the residual."""
+    nx, ny = 40, 33
+    inst = make_instance(nx, ny, seed=56, ea="lognormal", clamp="none")
+    inst.fixed[:] = 0
+    inst.fixed[0, 0] = inst.fixed[-1, -1] = 1
+    inst.f[inst.fixed.astype(bool)] = 0.0
+    S = system_of(inst)
+    sets = om.make_sets(nx, ny, 16)
+    fs = om.ForceLocalSolver(S, sets, 0)
+    r = np.random.default_rng(57).standard_normal(S.f.size) * S.free
+    kinds = set()
+    for I in range(sets.M):
+        nodes = om.relaxation_region(sets, I, 0)
+        dofs, Kd = _isolated_by_loops(inst, nodes)
+        assert np.array_equal(dofs, fs.idx[I])
+        w = np.linalg.eigvalsh(Kd)
+        nzero = int((w < 1e-10 * w.max()).sum())
+        kinds.add(nzero)
+        want = np.linalg.pinv(Kd, rcond=1e-10, hermitian=True) @ r[dofs]
+        got = fs.relax_region(I, r)
+        assert np.linalg.norm(got - want) <= 1e-9 * np.linalg.norm(want), (I, nzero)
+    # strips (each free node's motion across the strip, and a slide along it
+    # unless the strip holds a clamped node), floating regions (3) and regions
+    # pinned at one node (1) all occur
+    assert {1, 3} <= kinds and max(kinds) > 3, kinds
+    # the method's twelve-mode step runs on this lattice
+    m = om.Method(S, sets, overlap=0, modes=12)
+    st = m.step(S.u_c.copy())
+    assert np.all(np.isfinite(st.u_new))
 
 
 def test_modes_10_to_12_span_the_force_increment_products():
