@@ -139,6 +139,34 @@ def test_exact_solve_matches_oracle(nx, ny, E, ov):
     assert err <= 1e-8, err
 
 
+EXACT_LATTICES = {16: (45, 37), 32: (75, 70)}
+EXACT_SHAPES = [(16, 256, ov) for ov in (0, 1, 2, 4)] + \
+    [(32, nt, ov) for nt in (256, 512) for ov in (0, 1, 2, 4)] + [(32, 1024, 0)]
+_exact_refs = {}
+
+
+@pytest.mark.parametrize("E,nt,ov", EXACT_SHAPES)
+def test_every_exact_tile_instantiation_matches_oracle(E, nt, ov, monkeypatch):
+    """The exact local solve in every tile kernel that carries it: set edge 16
+    and 32, each thread count the launcher takes (default or TL_TILE_THREADS),
+    overlap 0, 1, 2, 4."""
+    monkeypatch.setenv("TL_TILE_THREADS", str(nt))
+    if E not in _exact_refs:
+        nx, ny = EXACT_LATTICES[E]
+        inst = make_instance(nx, ny, seed=100 + E, ea="lognormal")
+        _exact_refs[E] = (inst, solve(system_of(inst)))
+    inst, ref = _exact_refs[E]
+    lat = make_lattice(inst, E)
+    f = dev(inst.f)
+    u = torch.zeros_like(f)
+    info = tl.tl_solve(lat, f, u, precision=tl.TL_FP64, rtol=1e-10, overlap=ov_arg(ov),
+                       local_solve=tl.TL_LOCAL_EXACT)
+    assert info["status"] == tl.TL_OK
+    assert max(info["rel_res_l1"], info["rel_res_l2"]) <= 1e-10
+    err = np.linalg.norm(u.cpu().numpy().reshape(-1) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-8, err
+
+
 def test_factors_built_once_and_counted():
     nx, ny, E = 90, 70, 16
     inst = make_instance(nx, ny, seed=50, ea="lognormal")
