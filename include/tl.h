@@ -131,8 +131,10 @@ typedef struct {
     int32_t inner_iters;       /* relaxation PCG sweeps per set; 0 = default: 24
                                   with 64 x 64 sets, 20 for float64 with 32 x 32
                                   sets, else 16                                     */
-    int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default: 100, or
-                                  200 for lattices of 16384 sets or more            */
+    int32_t coarse_iters;      /* upper-level PCG iteration cap; 0 = default: 100;
+                                  200 for lattices of 16384 sets or more; 20
+                                  (TL_FP64) or 25 (TL_MIXED) for lattices of at
+                                  most 256 sets                                     */
     double coarse_rtol;        /* upper-level PCG relative tolerance; 0 = default:
                                   0.05 for lattices of 16384 sets or more, else 0.15
                                   for float64 with sets of at most 32 x 32, else 0.1 */

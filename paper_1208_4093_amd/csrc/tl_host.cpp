@@ -166,9 +166,22 @@ constexpr int kDefaultOverlap = 2;
 //  - below that the float64 form with sets of at most 32 x 32 does better
 //    with a looser one, 0.15 (512^2 to 3000^2: 1-7 % faster), while with
 //    64 x 64 sets, and in the mixed form, 0.15 costs outer iterations
-//    (4096^2 float64 +4 %, 2048^2 mixed +27 %) and 0.1 stays.
+//    (4096^2 float64 +4 %, 2048^2 mixed +27 %) and 0.1 stays;
+//  - lattices of at most 256 sets (sides up to 512 with 32 x 32 sets) stop
+//    the upper-level PCG after 20 iterations in float64 and 25 in the mixed
+//    form.  Fused with others, a lattice's long upper-level solve holds the
+//    whole launch; capped, the 256-lattice batch of sides 32-512 runs 6 %
+//    (float64) and 3 % (mixed) faster on three seed sets of its lattices,
+//    with the same outer iterations to within a few.  At 1024 sets (1024^2)
+//    a cap of 20 costs outer iterations (float64 104 -> 172), so larger
+//    lattices keep 100.
 constexpr int kLargeUpperLevel = 16384;
-int default_coarse_iters(int M) { return M >= kLargeUpperLevel ? 200 : 100; }
+constexpr int kSmallUpperLevel = 256;
+int default_coarse_iters(int M, bool mixed) {
+  if (M >= kLargeUpperLevel) return 200;
+  if (M <= kSmallUpperLevel) return mixed ? 25 : 20;
+  return 100;
+}
 double default_coarse_rtol(int M, int E, bool mixed) {
   if (M >= kLargeUpperLevel) return 0.05;
   return !mixed && E <= 32 ? 0.15 : 0.1;
@@ -255,7 +268,7 @@ void make_iteration_args(const tl_lattice* L, Work* w, const Opts& o, const doub
   ca->tr_coef = o.trace ? o.trace->coef : nullptr;
   ca->ctrl = w->ctrl;
   ca->max_iters = o.max_iters;
-  ca->coarse_iters = o.coarse_iters > 0 ? o.coarse_iters : default_coarse_iters(L->g.M);
+  ca->coarse_iters = o.coarse_iters > 0 ? o.coarse_iters : default_coarse_iters(L->g.M, o.mixed);
   ca->coarse_rtol = o.coarse_rtol > 0.0 ? o.coarse_rtol : default_coarse_rtol(L->g.M, L->g.E, o.mixed);
   ca->rtol = o.rtol;
   ca->warm = env_int("TL_COARSE_WARM", 1);
