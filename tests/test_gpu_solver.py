@@ -269,6 +269,25 @@ def test_every_batched_tile_instantiation_matches_oracle(ov, precision):
         assert err <= 1e-8, (err, info)
 
 
+@pytest.mark.parametrize("precision,cap", [(0, 20), (1, 25)])
+def test_small_lattice_upper_level_cap(precision, cap):
+    """Lattices of at most 256 sets stop the upper-level PCG after 20
+    (float64) or 25 (mixed) iterations by default and still reach the oracle's
+    solution; an explicit cap overrides it."""
+    inst = make_instance(200, 150, seed=21, ea="lognormal")
+    us = solve(system_of(inst))
+    u, info, lat = gpu_solve(inst, 16, precision, 1e-10)
+    assert lat.sets <= 256
+    assert info["status"] == tl.TL_OK
+    assert info["coarse_iters"] <= cap * info["iters"]
+    err = np.linalg.norm(u.reshape(-1) - us) / np.linalg.norm(us)
+    assert err <= 1e-8, (err, info)
+    u2, info2, _ = gpu_solve(inst, 16, precision, 1e-10, coarse_iters=3)
+    assert info2["status"] == tl.TL_OK
+    assert info2["coarse_iters"] <= 3 * info2["iters"]
+    assert np.linalg.norm(u2.reshape(-1) - us) <= 1e-8 * np.linalg.norm(us)
+
+
 def test_energy_decreases_every_iteration():
     inst = make_instance(50, 41, seed=11, ea="lognormal")
     lat = make_lattice(inst, 16)
