@@ -54,7 +54,8 @@ HBM_PEAK_GBS = 8000.0
 # when every launch is timed.  The kernel split comes from one more solve
 # after the timed ones with every launch timed.
 PROFILE_STRIDE = 8
-# Host cores the CPU baseline may use: the GPU machine's CPU share is 16 cores.
+# Host cores the CPU baseline may use: at most 16 (the CPU share of one GPU on
+# an MI355X node).
 MAX_CPU_WORKERS = 16
 
 SINGLE = {
